@@ -1,0 +1,185 @@
+/*
+ * sem.h -- C ABI of the Hilbert-ordered spectral-element wave propagator for MI355X (gfx950).
+ *
+ * The library advances the 2D acoustic wave equation u_tt = div(c^2 grad u) + s on a
+ * conforming quadrilateral mesh with Gauss-Lobatto-Legendre (GLL) nodes of order p,
+ * with explicit leapfrog steps. Elements are relabelled along a space-filling curve and
+ * global nodes are relabelled by first touch in that element order, with each element's
+ * new nodes sorted by ascending degree (Araujo, Gross, Xavier-de-Souza 2021, Sec. 4.3).
+ * One time step gathers each element's nodal values, applies the tensor-product stiffness
+ * (derivative matrix D, geometric factors, D^T; Sec. 4.2, Eqs. deriv_u and R),
+ * scatter-adds into the global vector and applies the diagonal-mass-inverse update
+ * (Eq. u_change, with the point sources of Alg. 3).
+ *
+ * Conventions shared by every call
+ *   - All user-visible arrays use the ORIGINAL numbering: elements in input order; global
+ *     nodes numbered vertices first (node id = vertex id), then the p-1 interior nodes of
+ *     each edge in order of first appearance over (element, local edge 0..3) counted from
+ *     the edge's lower-id vertex, then the (p-1)^2 interior nodes of each element. The
+ *     internal relabelling never leaks through the ABI except via sem_get_permutations.
+ *   - Local edge k of a quad runs from corner k to corner (k+1)%4; corners are CCW.
+ *   - Return value of every int-returning call: SEM_OK (0) or a negative SEM_ERR_* code;
+ *     sem_last_error() then describes the failure. No C++ exception crosses the ABI.
+ *   - Host pointers (const double*, const int32_t* in sem_mesh, xy arrays, permutation
+ *     outputs) are read or written synchronously; the library copies inputs, the caller
+ *     keeps ownership. Device pointers (names ending in _dev) are borrowed for
+ *     stream-ordered use on the context's stream and must stay valid until that stream
+ *     has executed the call's work.
+ *   - A context is not thread-safe; calls on one context must be serialised.
+ */
+#ifndef SEM_H_
+#define SEM_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sem_ctx sem_ctx;
+
+enum sem_status {
+    SEM_OK = 0,
+    SEM_ERR_INVALID_ARG = -1,  /* null pointer, out-of-range id or option, bad size   */
+    SEM_ERR_BAD_MESH = -2,     /* non-positive Jacobian, non-conforming or CW element */
+    SEM_ERR_UNSTABLE_DT = -3,  /* dt >= 2/sqrt(lambda_max(M^-1 K)) (power iteration) */
+    SEM_ERR_HIP = -4,          /* a HIP runtime call failed                           */
+    SEM_ERR_OOM = -5,          /* device or host allocation failed                    */
+    SEM_ERR_NO_DEVICE = -6     /* compute call on a host-only context                 */
+};
+
+enum sem_precision { SEM_F32 = 0, SEM_F64 = 1 };
+enum sem_elem_order { SEM_ORDER_HILBERT = 0, SEM_ORDER_MORTON = 1, SEM_ORDER_LEX = 2,
+                      SEM_ORDER_RANDOM = 3 };
+enum sem_node_order { SEM_NODES_FIRST_TOUCH = 0, SEM_NODES_ORIGINAL = 1 };
+enum sem_field { SEM_FIELD_U = 0, SEM_FIELD_V = 1 };
+
+/* Input mesh (host arrays, original numbering). */
+typedef struct {
+    int64_t n_vertices;
+    const double* vxy;       /* [n_vertices][2] vertex coordinates                    */
+    int64_t n_elements;
+    const int32_t* quad;     /* [n_elements][4] CCW corner vertex ids                  */
+    const double* c2;        /* [n_elements] squared wave speed, > 0                   */
+} sem_mesh;
+
+/* Options of sem_create. Zero-initialise, then set what is needed. */
+typedef struct {
+    int32_t p;               /* GLL order, 1..7                                         */
+    int32_t precision;       /* sem_precision                                           */
+    int32_t elem_order;      /* sem_elem_order                                          */
+    int32_t node_order;      /* sem_node_order; device contexts need FIRST_TOUCH        */
+    uint64_t seed;           /* seed of SEM_ORDER_RANDOM                                */
+    int32_t n_shots;         /* independent wavefields advanced together, >= 1          */
+    int32_t device;          /* HIP device ordinal; -1 = host-only (setup, no compute)  */
+    double dt;               /* time step; 0 = cfl * min_e(dx_min,e / c_e)              */
+    double cfl;              /* CFL number of the default dt; 0 = 0.3                  */
+    void* stream;            /* hipStream_t for all device work; NULL = default stream */
+    int32_t tile_elems;      /* elements per workgroup tile; 0 = automatic              */
+    int32_t shot_lanes;      /* shots per element inside a workgroup; 0 = automatic     */
+} sem_options;
+
+typedef struct {
+    int64_t n_elements;
+    int64_t n_nodes;
+    int32_t p;
+    int32_t n_shots;
+    int32_t precision;
+    int32_t n_sources;       /* after merging sources on the same (node, shot)         */
+    int32_t n_receivers;
+    int32_t tile_elems;
+    int32_t shot_lanes;
+    int32_t max_owned_nodes; /* largest owned-node range of a tile                      */
+    int64_t n_tiles;
+    int64_t halo_elements;   /* sum over tiles of neighbour elements recomputed         */
+    int64_t step;            /* steps taken since the last reset                        */
+    double dt;
+    double dt_stable;        /* 2/sqrt(lambda_max) from power iteration (0 host-only)  */
+    double lambda_max;
+    double alg_bytes_per_step;  /* algorithmic HBM bytes of one step (see DESIGN)     */
+    double alg_flops_per_step;
+    double setup_seconds;    /* host setup wall time (numbering, reorder, geometry)   */
+    double reorder_seconds;  /* part of setup spent on element and node reordering    */
+} sem_info;
+
+/* Build the context: validate the mesh, number the GLL nodes, reorder elements and
+ * nodes, compute geometric factors, mass and dt, allocate device state (u = v = 0).
+ * Errors: INVALID_ARG, BAD_MESH, UNSTABLE_DT (explicit dt too large), HIP, OOM.
+ * On error *out is set to NULL and sem_create_error() returns the message. */
+int sem_create(const sem_mesh* mesh, const sem_options* opt, sem_ctx** out);
+
+/* Message of the last failed sem_create in this thread. */
+const char* sem_create_error(void);
+
+int sem_get_info(const sem_ctx* ctx, sem_info* info);
+
+/* new -> old permutations of the elements [n_elements] and global nodes [n_nodes]
+ * (host buffers owned by the caller). Either pointer may be NULL. */
+int sem_get_permutations(const sem_ctx* ctx, int32_t* elem_new2old, int32_t* node_new2old);
+
+/* Coordinates of the global nodes, original numbering, [n_nodes][2] host buffer. */
+int sem_get_node_coords(const sem_ctx* ctx, double* xy);
+
+/* Point sources (Alg. 3): source i sits at the global node nearest to xy[i] (equal
+ * distances -> lowest original id), belongs to shot shot[i], and injects a Ricker
+ * wavelet r(t) = (1 - 2 a) exp(-a), a = (pi f0 (t - t0))^2, at t_n = n dt. Sources on the
+ * same (node, shot) add up. Replaces earlier sources. node_out (may be NULL) receives the
+ * snapped original node id of each source. */
+int sem_set_sources(sem_ctx* ctx, int32_t n, const double* xy, const int32_t* shot,
+                    double f0, double t0, int32_t* node_out);
+
+/* Receivers: the nearest global node to each xy (same tie rule); every shot records u at
+ * all receivers after each step. node_out as above. */
+int sem_set_receivers(sem_ctx* ctx, int32_t n, const double* xy, int32_t* node_out);
+
+/* Replace the model c^2 (host, original element order). Keeps dt; re-checks stability. */
+int sem_set_c2(sem_ctx* ctx, const double* c2);
+
+/* u = v = 0, step counter = 0. */
+int sem_reset(sem_ctx* ctx);
+
+/* Advance nsteps steps. traces_dev (may be NULL) is a device buffer
+ * [n_shots][n_receivers][nsteps] of the context precision; column j receives u after
+ * step j of this call. Asynchronous on the context stream. */
+int sem_run(sem_ctx* ctx, int64_t nsteps, void* traces_dev);
+
+/* One step without recording (sem_run(ctx, 1, NULL)). */
+int sem_step(sem_ctx* ctx);
+
+/* Copy the current field out of / into the context: device buffer [n_shots][n_nodes] of
+ * the context precision, ORIGINAL node numbering. For V the value is v^{n-1/2}. */
+int sem_get_field(sem_ctx* ctx, int32_t which, void* dev);
+int sem_set_field(sem_ctx* ctx, int32_t which, const void* dev);
+
+/* One application r = K u of the assembled stiffness (Eq. R with the second-order flux),
+ * both device buffers [n_shots][n_nodes] in original numbering. For operator checks. */
+int sem_apply_stiffness(sem_ctx* ctx, const void* u_dev, void* r_dev);
+
+/* Gradient of a loss of the receiver traces with respect to c^2 of every element.
+ * Runs the forward from rest for nsteps steps storing (u, v) every ckpt_every steps, then
+ * the discrete adjoint backwards segment by segment, recomputing each segment's forward
+ * states from its checkpoint. dL_dtraces_dev: device [n_shots][n_receivers][nsteps] of the
+ * context precision. grad_c2_dev: device [n_elements] double, original element order,
+ * overwritten. Leaves the context reset. */
+int sem_adjoint_gradient(sem_ctx* ctx, const void* dL_dtraces_dev, int64_t nsteps,
+                         int32_t ckpt_every, double* grad_c2_dev);
+
+/* Wait for all work queued on the context stream. */
+int sem_synchronize(sem_ctx* ctx);
+
+/* Position of every cell (cx[i], cy[i]) along the generalized Hilbert curve over a W x H
+ * cell grid (the element key of the Hilbert order, Sec. 4.3 step 2). Host arrays. */
+int sem_hilbert_index(int64_t W, int64_t H, int64_t n, const int64_t* cx, const int64_t* cy,
+                      int64_t* index_out);
+
+/* Description of the last error on this context (never NULL). */
+const char* sem_last_error(const sem_ctx* ctx);
+
+/* Free the context and its device memory (synchronises its stream first). */
+void sem_destroy(sem_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SEM_H_ */

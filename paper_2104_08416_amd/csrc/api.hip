@@ -1,0 +1,816 @@
+// api.hip -- the extern "C" boundary: context lifetime, device memory, step driver,
+// sources/receivers, field I/O, stiffness apply and the checkpointed adjoint gradient.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <random>
+#include <string>
+#include <vector>
+
+#include "../../include/sem.h"
+#include "kernels.h"
+#include "plan.h"
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace
+
+struct sem_ctx {
+    sem::Plan plan;
+    sem::MeshIn mesh;                 // pointers valid only during sem_create
+    int precision = SEM_F32;
+    int S = 1, SL = 1;
+    int device = -1;
+    bool host_only = true;
+    hipStream_t stream = nullptr;
+    std::string err;
+    size_t wsize = 4;                 // bytes per state word
+    // device mesh/tiling
+    DevBuf conn, G, c2, dtminv, tile_eb, tile_nb, halo_b, halo, n2o_node, n2o_elem;
+    // state
+    DevBuf u[2], v;
+    int cur = 0;
+    int64_t step = 0;
+    // sources / receivers (per-tile CSR on device)
+    DevBuf src_b, src_loc, src_shot, src_w, rec_b, rec_loc, rec_idx;
+    int32_t n_src = 0, n_rec = 0;
+    double f0 = 10.0, t0 = 0.1;
+    double lambda_max = 0.0, dt_stable = 0.0;
+    double setup_seconds = 0.0;
+    std::vector<DevBuf*> owned;       // every DevBuf to free at destroy
+    std::vector<DevBuf> extra;        // scratch owned by the adjoint driver
+};
+
+namespace {
+
+#define SEM_HIP(ctx, call)                                                                        \
+    do {                                                                                          \
+        hipError_t e_ = (call);                                                                   \
+        if (e_ != hipSuccess) {                                                                   \
+            (ctx)->err = std::string(#call) + ": " + hipGetErrorString(e_);                       \
+            return e_ == hipErrorOutOfMemory ? SEM_ERR_OOM : SEM_ERR_HIP;                         \
+        }                                                                                         \
+    } while (0)
+
+int fail(sem_ctx* c, int code, const std::string& msg) {
+    c->err = msg;
+    return code;
+}
+
+hipError_t dev_alloc(DevBuf& b, size_t bytes) {
+    if (b.p) { hipFree(b.p); b.p = nullptr; b.bytes = 0; }
+    if (bytes == 0) return hipSuccess;
+    hipError_t e = hipMalloc(&b.p, bytes);
+    if (e == hipSuccess) b.bytes = bytes;
+    return e;
+}
+
+void dev_free(DevBuf& b) {
+    if (b.p) hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+}
+
+template <typename Src>
+hipError_t upload(sem_ctx* c, DevBuf& b, const std::vector<Src>& v) {
+    hipError_t e = dev_alloc(b, v.size() * sizeof(Src));
+    if (e != hipSuccess || v.empty()) return e;
+    e = hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(Src), hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(c->stream);
+}
+
+// cast a double vector to the context precision and upload
+hipError_t upload_real(sem_ctx* c, DevBuf& b, const std::vector<double>& v, double scale = 1.0) {
+    if (c->precision == SEM_F64) {
+        if (scale == 1.0) return upload(c, b, v);
+        std::vector<double> t(v.size());
+        for (size_t i = 0; i < v.size(); ++i) t[i] = v[i] * scale;
+        return upload(c, b, t);
+    }
+    std::vector<float> t(v.size());
+    for (size_t i = 0; i < v.size(); ++i) t[i] = (float)(v[i] * scale);
+    return upload(c, b, t);
+}
+
+template <typename T>
+sem::StepArgs<T> base_args(sem_ctx* c) {
+    sem::StepArgs<T> a;
+    std::memset(&a, 0, sizeof(a));
+    const sem::Plan& P = c->plan;
+    a.conn = (const int32_t*)c->conn.p;
+    a.G = (const T*)c->G.p;
+    a.c2 = (const T*)c->c2.p;
+    a.dtminv = (const T*)c->dtminv.p;
+    a.E = P.ne;
+    a.S = c->S;
+    a.conn_bytes = (uint32_t)c->conn.bytes;
+    a.G_bytes = (uint32_t)c->G.bytes;
+    a.c2_bytes = (uint32_t)c->c2.bytes;
+    a.state_bytes = (uint32_t)((size_t)P.nn * c->S * c->wsize);
+    a.tile_eb = (const int32_t*)c->tile_eb.p;
+    a.tile_nb = (const int32_t*)c->tile_nb.p;
+    a.halo_b = (const int32_t*)c->halo_b.p;
+    a.halo = (const int32_t*)c->halo.p;
+    a.n_slices = c->S / c->SL;
+    a.dt = (T)P.dt;
+    a.n_rec = c->n_rec;
+    a.f0 = c->f0;
+    a.t0 = c->t0;
+    for (int i = 0; i < P.n * P.n; ++i) a.D[i] = (T)P.D[i];
+    return a;
+}
+
+size_t lds_bytes(const sem_ctx* c) { return (size_t)c->plan.max_owned * c->SL * c->wsize; }
+
+template <typename T>
+int launch(sem_ctx* c, const sem::StepArgs<T>& a) {
+    const int64_t nt = (int64_t)c->plan.tile_eb.size() - 1;
+    SEM_HIP(c, sem::launch_step<T>(c->plan.p, c->SL, nt, lds_bytes(c), a, c->stream));
+    return SEM_OK;
+}
+
+// one forward step u[cur] -> u[cur^1]; optional trace column
+template <typename T>
+int do_step(sem_ctx* c, T* trace, int64_t cols, int64_t col) {
+    sem::StepArgs<T> a = base_args<T>(c);
+    a.u_in = (const T*)c->u[c->cur].p;
+    a.u_out = (T*)c->u[c->cur ^ 1].p;
+    a.v = (T*)c->v.p;
+    a.mode = 0;
+    if (c->n_src > 0) {
+        a.src_b = (const int32_t*)c->src_b.p;
+        a.src_loc = (const int32_t*)c->src_loc.p;
+        a.src_shot = (const int32_t*)c->src_shot.p;
+        a.src_w = (const T*)c->src_w.p;
+        a.src_t = (double)c->step * c->plan.dt;
+    }
+    if (trace && c->n_rec > 0) {
+        a.rec_b = (const int32_t*)c->rec_b.p;
+        a.rec_loc = (const int32_t*)c->rec_loc.p;
+        a.rec_idx = (const int32_t*)c->rec_idx.p;
+        a.trace = trace;
+        a.trace_cols = cols;
+        a.trace_col = col;
+    }
+    int rc = launch<T>(c, a);
+    if (rc != SEM_OK) return rc;
+    c->cur ^= 1;
+    c->step += 1;
+    return SEM_OK;
+}
+
+template <typename T>
+int zero_state(sem_ctx* c) {
+    const int64_t n = c->plan.nn * (int64_t)c->S;
+    for (int k = 0; k < 2; ++k) SEM_HIP(c, sem::launch_fill<T>((T*)c->u[k].p, T(0), n, c->stream));
+    SEM_HIP(c, sem::launch_fill<T>((T*)c->v.p, T(0), n, c->stream));
+    c->cur = 0;
+    c->step = 0;
+    return SEM_OK;
+}
+
+// lambda_max(M^-1 K) by power iteration with the stiffness-apply mode of the step kernel
+template <typename T>
+int power_iteration(sem_ctx* c, int iters) {
+    const int64_t n = c->plan.nn * (int64_t)c->S;
+    std::vector<T> x0(n);
+    std::mt19937_64 rng(12345);
+    std::uniform_real_distribution<double> U(-1.0, 1.0);
+    for (auto& v : x0) v = (T)U(rng);
+    SEM_HIP(c, hipMemcpyAsync(c->u[0].p, x0.data(), n * sizeof(T), hipMemcpyHostToDevice, c->stream));
+    DevBuf nrm;
+    SEM_HIP(c, dev_alloc(nrm, sizeof(double)));
+    auto sumsq = [&](const T* x, double& out) -> int {
+        SEM_HIP(c, sem::launch_fill<double>((double*)nrm.p, 0.0, 1, c->stream));
+        SEM_HIP(c, sem::launch_sumsq<T>(x, n, (double*)nrm.p, c->stream));
+        SEM_HIP(c, hipMemcpyAsync(&out, nrm.p, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        SEM_HIP(c, hipStreamSynchronize(c->stream));
+        return SEM_OK;
+    };
+    double nx = 0.0;
+    int rc = sumsq((const T*)c->u[0].p, nx);
+    if (rc) { dev_free(nrm); return rc; }
+    SEM_HIP(c, sem::launch_scale<T>((T*)c->u[0].p, 1.0 / std::sqrt(nx), n, c->stream));
+    double lam = 0.0;
+    for (int it = 0; it < iters; ++it) {
+        sem::StepArgs<T> a = base_args<T>(c);
+        a.u_in = (const T*)c->u[0].p;
+        a.mode = 2;
+        a.r_out = (T*)c->u[1].p;
+        rc = launch<T>(c, a);
+        if (rc) { dev_free(nrm); return rc; }
+        double ny = 0.0;
+        rc = sumsq((const T*)c->u[1].p, ny);
+        if (rc) { dev_free(nrm); return rc; }
+        ny = std::sqrt(ny);
+        lam = ny / c->plan.dt;                // |dt M^-1 K x| / dt with |x| = 1
+        if (!(ny > 0.0)) break;
+        SEM_HIP(c, sem::launch_scale<T>((T*)c->u[1].p, 1.0 / ny, n, c->stream));
+        std::swap(c->u[0], c->u[1]);
+    }
+    dev_free(nrm);
+    c->lambda_max = lam;
+    c->dt_stable = lam > 0.0 ? 2.0 / std::sqrt(lam) : INFINITY;
+    return zero_state<T>(c);
+}
+
+int check_ctx(const sem_ctx* c) { return c ? SEM_OK : SEM_ERR_INVALID_ARG; }
+
+int need_device(sem_ctx* c) {
+    if (c->host_only) return fail(c, SEM_ERR_NO_DEVICE, "context was created host-only (device = -1)");
+    return SEM_OK;
+}
+
+int set_device(sem_ctx* c) {
+    SEM_HIP(c, hipSetDevice(c->device));
+    return SEM_OK;
+}
+
+template <typename T>
+int upload_mesh(sem_ctx* c) {
+    const sem::Plan& P = c->plan;
+    // element-blocked device layouts [E/64][component][q][64] (padding repeats element 0)
+    const int64_t nq = P.nq, nblk = (P.ne + 63) / 64;
+    {
+        std::vector<int32_t> cb((size_t)nblk * nq * 64);
+        std::vector<double> gb((size_t)nblk * 3 * nq * 64);
+        for (int64_t e = 0; e < nblk * 64; ++e) {
+            const int64_t src = e < P.ne ? e : 0, b = e / 64, l = e % 64;
+            for (int64_t q = 0; q < nq; ++q) {
+                cb[(b * nq + q) * 64 + l] = P.conn_soa[q * P.ne + src];
+                for (int64_t k = 0; k < 3; ++k)
+                    gb[((b * 3 + k) * nq + q) * 64 + l] = P.G_soa[(k * nq + q) * P.ne + src];
+            }
+        }
+        SEM_HIP(c, upload(c, c->conn, cb));
+        SEM_HIP(c, upload_real(c, c->G, gb));
+    }
+    SEM_HIP(c, upload_real(c, c->c2, P.c2));
+    SEM_HIP(c, upload_real(c, c->dtminv, P.minv, P.dt));
+    SEM_HIP(c, upload(c, c->tile_eb, P.tile_eb));
+    SEM_HIP(c, upload(c, c->tile_nb, P.tile_nb));
+    SEM_HIP(c, upload(c, c->halo_b, P.halo_b));
+    std::vector<int32_t> h = P.halo;
+    if (h.empty()) h.push_back(0);
+    SEM_HIP(c, upload(c, c->halo, h));
+    SEM_HIP(c, upload(c, c->n2o_node, P.node_new2old));
+    SEM_HIP(c, upload(c, c->n2o_elem, P.elem_new2old));
+    const size_t state = (size_t)P.nn * c->S * sizeof(T);
+    for (int k = 0; k < 2; ++k) SEM_HIP(c, dev_alloc(c->u[k], state));
+    SEM_HIP(c, dev_alloc(c->v, state));
+    return zero_state<T>(c);
+}
+
+int pick_shot_lanes(int S, int requested) {
+    if (requested > 0) return requested;
+    int sl = 1;
+    while (sl < 16 && S % (sl * 2) == 0) sl *= 2;
+    return sl;
+}
+
+int pick_tile(int p, int sl, int precision, int requested) {
+    if (requested > 0) return requested;
+    // keep the LDS accumulator of a workgroup near 32 KB: owned nodes ~ p^2 per element
+    const int word = precision == SEM_F64 ? 8 : 4;
+    int t = 32768 / (p * p * sl * word);
+    t = std::max(16, std::min(256, t));
+    return t;
+}
+
+// owning tile of a new node id
+int64_t tile_of_node(const sem::Plan& P, int32_t v) {
+    auto it = std::upper_bound(P.tile_nb.begin(), P.tile_nb.end(), v);
+    return (int64_t)(it - P.tile_nb.begin()) - 1;
+}
+
+template <typename T>
+int set_sources_t(sem_ctx* c, int32_t n, const double* xy, const int32_t* shot, int32_t* node_out) {
+    const sem::Plan& P = c->plan;
+    const int64_t nt = (int64_t)P.tile_eb.size() - 1;
+    struct Ent { int64_t tile; int32_t loc; int32_t shot; double w; };
+    std::vector<Ent> ents;
+    for (int32_t i = 0; i < n; ++i) {
+        const int32_t old = sem::nearest_node(P, xy[2 * i], xy[2 * i + 1]);
+        if (node_out) node_out[i] = old;
+        const int32_t nw = P.node_old2new[old];
+        const int64_t t = tile_of_node(P, nw);
+        ents.push_back({t, nw - P.tile_nb[t], shot[i], 1.0});
+    }
+    std::sort(ents.begin(), ents.end(), [](const Ent& a, const Ent& b) {
+        if (a.tile != b.tile) return a.tile < b.tile;
+        if (a.loc != b.loc) return a.loc < b.loc;
+        return a.shot < b.shot;
+    });
+    std::vector<Ent> merged;
+    for (const Ent& e : ents) {
+        if (!merged.empty() && merged.back().tile == e.tile && merged.back().loc == e.loc &&
+            merged.back().shot == e.shot)
+            merged.back().w += e.w;
+        else
+            merged.push_back(e);
+    }
+    std::vector<int32_t> b(nt + 1, 0), loc, sh;
+    std::vector<double> w;
+    for (const Ent& e : merged) {
+        b[e.tile + 1]++;
+        loc.push_back(e.loc);
+        sh.push_back(e.shot);
+        w.push_back(e.w);
+    }
+    for (int64_t t = 0; t < nt; ++t) b[t + 1] += b[t];
+    c->n_src = (int32_t)merged.size();
+    if (c->host_only) return SEM_OK;
+    SEM_HIP(c, upload(c, c->src_b, b));
+    SEM_HIP(c, upload(c, c->src_loc, loc));
+    SEM_HIP(c, upload(c, c->src_shot, sh));
+    SEM_HIP(c, upload_real(c, c->src_w, w));
+    return SEM_OK;
+}
+
+template <typename T>
+int set_receivers_t(sem_ctx* c, int32_t n, const double* xy, int32_t* node_out) {
+    const sem::Plan& P = c->plan;
+    const int64_t nt = (int64_t)P.tile_eb.size() - 1;
+    struct Ent { int64_t tile; int32_t loc; int32_t r; };
+    std::vector<Ent> ents;
+    for (int32_t i = 0; i < n; ++i) {
+        const int32_t old = sem::nearest_node(P, xy[2 * i], xy[2 * i + 1]);
+        if (node_out) node_out[i] = old;
+        const int32_t nw = P.node_old2new[old];
+        const int64_t t = tile_of_node(P, nw);
+        ents.push_back({t, nw - P.tile_nb[t], i});
+    }
+    std::stable_sort(ents.begin(), ents.end(), [](const Ent& a, const Ent& b) { return a.tile < b.tile; });
+    std::vector<int32_t> b(nt + 1, 0), loc, idx;
+    for (const Ent& e : ents) {
+        b[e.tile + 1]++;
+        loc.push_back(e.loc);
+        idx.push_back(e.r);
+    }
+    for (int64_t t = 0; t < nt; ++t) b[t + 1] += b[t];
+    c->n_rec = n;
+    if (c->host_only) return SEM_OK;
+    SEM_HIP(c, upload(c, c->rec_b, b));
+    SEM_HIP(c, upload(c, c->rec_loc, loc.empty() ? std::vector<int32_t>{0} : loc));
+    SEM_HIP(c, upload(c, c->rec_idx, idx.empty() ? std::vector<int32_t>{0} : idx));
+    return SEM_OK;
+}
+
+template <typename T>
+int run_t(sem_ctx* c, int64_t nsteps, void* traces) {
+    for (int64_t j = 0; j < nsteps; ++j) {
+        int rc = do_step<T>(c, (T*)traces, nsteps, j);
+        if (rc) return rc;
+    }
+    return SEM_OK;
+}
+
+template <typename T>
+int apply_t(sem_ctx* c, const void* u_dev, void* r_dev) {
+    const int64_t N = c->plan.nn;
+    DevBuf tin, tout;
+    const size_t bytes = (size_t)N * c->S * sizeof(T);
+    SEM_HIP(c, dev_alloc(tin, bytes));
+    hipError_t e = dev_alloc(tout, bytes);
+    if (e != hipSuccess) { dev_free(tin); SEM_HIP(c, e); }
+    int rc = SEM_OK;
+    do {
+        hipError_t h = sem::launch_nodes_from_original<T>((const T*)u_dev, (T*)tin.p,
+                                                          (const int32_t*)c->n2o_node.p, N, c->S, c->stream);
+        if (h != hipSuccess) { rc = fail(c, SEM_ERR_HIP, hipGetErrorString(h)); break; }
+        sem::StepArgs<T> a = base_args<T>(c);
+        a.u_in = (const T*)tin.p;
+        a.mode = 1;
+        a.r_out = (T*)tout.p;
+        rc = launch<T>(c, a);
+        if (rc) break;
+        h = sem::launch_nodes_to_original<T>((const T*)tout.p, (T*)r_dev, (const int32_t*)c->n2o_node.p,
+                                             N, c->S, c->stream);
+        if (h != hipSuccess) { rc = fail(c, SEM_ERR_HIP, hipGetErrorString(h)); break; }
+        h = hipStreamSynchronize(c->stream);
+        if (h != hipSuccess) { rc = fail(c, SEM_ERR_HIP, hipGetErrorString(h)); break; }
+    } while (false);
+    dev_free(tin);
+    dev_free(tout);
+    return rc;
+}
+
+// Forward with checkpoints, then the adjoint recurrence backwards segment by segment.
+// The adjoint state w^j is advanced by the same step kernel with the trace gradient
+// injected at the receivers (amplitude dL/dd[s][r][N-1-j] / dt^2); while it gathers
+// w^j for its stiffness apply, it also gathers u^{N-j} from the recomputed segment and
+// accumulates (Khat_e w^j_e) . u^{N-j}_e per element, which is mu^{n+1} Khat_e u^n with
+// n = N - j. The gradient is -dt^2 times that sum.
+template <typename T>
+int adjoint_t(sem_ctx* c, const void* dL, int64_t N, int32_t C, double* grad_out) {
+    const sem::Plan& P = c->plan;
+    const int64_t nnS = P.nn * (int64_t)c->S;
+    const size_t sb = (size_t)nnS * sizeof(T);
+    const int64_t nck = (N + C - 1) / C;
+    std::vector<DevBuf> ck_u(nck), ck_v(nck), seg(C);
+    DevBuf w[2], vw, acc;
+    auto cleanup = [&]() {
+        for (auto& b : ck_u) dev_free(b);
+        for (auto& b : ck_v) dev_free(b);
+        for (auto& b : seg) dev_free(b);
+        dev_free(w[0]); dev_free(w[1]); dev_free(vw); dev_free(acc);
+    };
+    int rc = SEM_OK;
+#define ADJ_HIP(call)                                                                             \
+    do {                                                                                          \
+        hipError_t e_ = (call);                                                                   \
+        if (e_ != hipSuccess) {                                                                   \
+            cleanup();                                                                            \
+            c->err = std::string(#call) + ": " + hipGetErrorString(e_);                           \
+            return e_ == hipErrorOutOfMemory ? SEM_ERR_OOM : SEM_ERR_HIP;                         \
+        }                                                                                         \
+    } while (0)
+    for (int64_t k = 0; k < nck; ++k) {
+        ADJ_HIP(dev_alloc(ck_u[k], sb));
+        ADJ_HIP(dev_alloc(ck_v[k], sb));
+    }
+    for (int32_t i = 0; i < C; ++i) ADJ_HIP(dev_alloc(seg[i], sb));
+    ADJ_HIP(dev_alloc(w[0], sb));
+    ADJ_HIP(dev_alloc(w[1], sb));
+    ADJ_HIP(dev_alloc(vw, sb));
+    ADJ_HIP(dev_alloc(acc, (size_t)P.ne * sizeof(double)));
+
+    // forward from rest, checkpoint (u^{kC}, v^{kC-1/2})
+    rc = zero_state<T>(c);
+    if (rc) { cleanup(); return rc; }
+    for (int64_t k = 0; k < nck; ++k) {
+        ADJ_HIP(hipMemcpyAsync(ck_u[k].p, c->u[c->cur].p, sb, hipMemcpyDeviceToDevice, c->stream));
+        ADJ_HIP(hipMemcpyAsync(ck_v[k].p, c->v.p, sb, hipMemcpyDeviceToDevice, c->stream));
+        const int64_t steps = std::min<int64_t>(C, N - k * C);
+        for (int64_t i = 0; i < steps; ++i) {
+            rc = do_step<T>(c, nullptr, 0, 0);
+            if (rc) { cleanup(); return rc; }
+        }
+    }
+    ADJ_HIP(sem::launch_fill<T>((T*)w[0].p, T(0), nnS, c->stream));
+    ADJ_HIP(sem::launch_fill<T>((T*)w[1].p, T(0), nnS, c->stream));
+    ADJ_HIP(sem::launch_fill<T>((T*)vw.p, T(0), nnS, c->stream));
+    ADJ_HIP(sem::launch_fill<double>((double*)acc.p, 0.0, P.ne, c->stream));
+    int wc = 0;
+    const T inv_dt2 = (T)(1.0 / (P.dt * P.dt));
+    auto adjoint_step = [&](int64_t j, const T* upair) -> int {
+        sem::StepArgs<T> a = base_args<T>(c);
+        a.u_in = (const T*)w[wc].p;
+        a.u_out = (T*)w[wc ^ 1].p;
+        a.v = (T*)vw.p;
+        a.mode = 0;
+        if (c->n_rec > 0) {
+            a.rec_b = (const int32_t*)c->rec_b.p;
+            a.rec_loc = (const int32_t*)c->rec_loc.p;
+            a.rec_idx = (const int32_t*)c->rec_idx.p;
+            a.inj = (const T*)dL;
+            a.inj_cols = N;
+            a.inj_col = N - 1 - j;
+            a.inj_scale = inv_dt2;
+        }
+        if (upair) {
+            a.u_pair = upair;
+            a.grad = (double*)acc.p;
+        }
+        int r = launch<T>(c, a);
+        wc ^= 1;
+        return r;
+    };
+    rc = adjoint_step(0, nullptr);                  // w^0 = 0 pairs with nothing
+    if (rc) { cleanup(); return rc; }
+    // segments last to first; segment k holds u^{kC} .. u^{kC+C-1}
+    for (int64_t k = nck - 1; k >= 0; --k) {
+        const int64_t n0 = k * C;
+        const int64_t n1 = std::min<int64_t>(n0 + C - 1, N - 1);   // last state needed
+        ADJ_HIP(hipMemcpyAsync(seg[0].p, ck_u[k].p, sb, hipMemcpyDeviceToDevice, c->stream));
+        ADJ_HIP(hipMemcpyAsync(c->v.p, ck_v[k].p, sb, hipMemcpyDeviceToDevice, c->stream));
+        for (int64_t n = n0; n < n1; ++n) {         // u^{n+1} from u^n
+            sem::StepArgs<T> a = base_args<T>(c);
+            a.u_in = (const T*)seg[n - n0].p;
+            a.u_out = (T*)seg[n - n0 + 1].p;
+            a.v = (T*)c->v.p;
+            a.mode = 0;
+            if (c->n_src > 0) {
+                a.src_b = (const int32_t*)c->src_b.p;
+                a.src_loc = (const int32_t*)c->src_loc.p;
+                a.src_shot = (const int32_t*)c->src_shot.p;
+                a.src_w = (const T*)c->src_w.p;
+                a.src_t = (double)n * P.dt;
+            }
+            rc = launch<T>(c, a);
+            if (rc) { cleanup(); return rc; }
+        }
+        for (int64_t n = n1; n >= std::max<int64_t>(n0, 1); --n) {
+            rc = adjoint_step(N - n, (const T*)seg[n - n0].p);
+            if (rc) { cleanup(); return rc; }
+        }
+    }
+    ADJ_HIP(sem::launch_grad_to_original((const double*)acc.p, grad_out, (const int32_t*)c->n2o_elem.p,
+                                         P.ne, -P.dt * P.dt, c->stream));
+    ADJ_HIP(hipStreamSynchronize(c->stream));
+    cleanup();
+#undef ADJ_HIP
+    return zero_state<T>(c);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* sem_create_error(void) { return g_create_error.c_str(); }
+
+int sem_create(const sem_mesh* mesh, const sem_options* opt, sem_ctx** out) {
+    g_create_error.clear();
+    if (!out) { g_create_error = "out is NULL"; return SEM_ERR_INVALID_ARG; }
+    *out = nullptr;
+    if (!mesh || !opt) { g_create_error = "mesh or options is NULL"; return SEM_ERR_INVALID_ARG; }
+    if (opt->precision != SEM_F32 && opt->precision != SEM_F64) {
+        g_create_error = "precision must be SEM_F32 or SEM_F64";
+        return SEM_ERR_INVALID_ARG;
+    }
+    if (opt->n_shots < 1) { g_create_error = "n_shots must be >= 1"; return SEM_ERR_INVALID_ARG; }
+    if (opt->p < 1 || opt->p > sem::kMaxP) { g_create_error = "p must be in 1..7"; return SEM_ERR_INVALID_ARG; }
+    if (opt->tile_elems < 0 || opt->shot_lanes < 0) {
+        g_create_error = "tile_elems and shot_lanes must be >= 0";
+        return SEM_ERR_INVALID_ARG;
+    }
+    if (opt->device >= 0 && opt->node_order != SEM_NODES_FIRST_TOUCH) {
+        g_create_error = "device contexts need node_order = SEM_NODES_FIRST_TOUCH (owned node ranges)";
+        return SEM_ERR_INVALID_ARG;
+    }
+    sem_ctx* c = new (std::nothrow) sem_ctx();
+    if (!c) { g_create_error = "host allocation failed"; return SEM_ERR_OOM; }
+    const auto t0 = std::chrono::steady_clock::now();
+    c->precision = opt->precision;
+    c->wsize = opt->precision == SEM_F64 ? 8 : 4;
+    c->S = opt->n_shots;
+    c->SL = pick_shot_lanes(c->S, opt->shot_lanes);
+    if (c->SL < 1 || c->SL > 64 || (c->SL & (c->SL - 1)) || c->S % c->SL) {
+        g_create_error = "shot_lanes must be a power of two <= 64 dividing n_shots";
+        delete c;
+        return SEM_ERR_INVALID_ARG;
+    }
+    c->device = opt->device;
+    c->host_only = opt->device < 0;
+    c->stream = (hipStream_t)opt->stream;
+    sem::MeshIn m;
+    m.nv = mesh->n_vertices;
+    m.ne = mesh->n_elements;
+    m.vxy = mesh->vxy;
+    m.quad = mesh->quad;
+    m.c2 = mesh->c2;
+    sem::PlanOptions po;
+    po.p = opt->p;
+    po.elem_order = opt->elem_order;
+    po.node_order = opt->node_order;
+    po.seed = opt->seed;
+    po.dt = opt->dt;
+    po.cfl = opt->cfl;
+    po.tile_elems = pick_tile(opt->p, c->SL, opt->precision, opt->tile_elems);
+    int code = SEM_OK;
+    std::string err;
+    try {
+        err = sem::build_plan(m, po, c->plan, code);
+    } catch (const std::bad_alloc&) {
+        err = "host allocation failed during setup";
+        code = SEM_ERR_OOM;
+    } catch (const std::exception& ex) {
+        err = ex.what();
+        code = SEM_ERR_INVALID_ARG;
+    }
+    if (!err.empty()) {
+        g_create_error = err;
+        delete c;
+        return code;
+    }
+    c->setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (!c->host_only) {
+        int rc = set_device(c);
+        if (rc == SEM_OK) rc = c->precision == SEM_F64 ? upload_mesh<double>(c) : upload_mesh<float>(c);
+        if (rc == SEM_OK) rc = c->precision == SEM_F64 ? power_iteration<double>(c, 60)
+                                                       : power_iteration<float>(c, 60);
+        if (rc == SEM_OK && !(c->plan.dt < c->dt_stable)) {
+            rc = SEM_ERR_UNSTABLE_DT;
+            c->err = "dt = " + std::to_string(c->plan.dt) + " exceeds the stability limit " +
+                     std::to_string(c->dt_stable);
+        }
+        if (rc != SEM_OK) {
+            g_create_error = c->err;
+            sem_destroy(c);
+            return rc;
+        }
+    }
+    *out = c;
+    return SEM_OK;
+}
+
+int sem_get_info(const sem_ctx* c, sem_info* info) {
+    if (!c || !info) return SEM_ERR_INVALID_ARG;
+    const sem::Plan& P = c->plan;
+    std::memset(info, 0, sizeof(*info));
+    info->n_elements = P.ne;
+    info->n_nodes = P.nn;
+    info->p = P.p;
+    info->n_shots = c->S;
+    info->precision = c->precision;
+    info->n_sources = c->n_src;
+    info->n_receivers = c->n_rec;
+    info->tile_elems = P.tile_elems;
+    info->shot_lanes = c->SL;
+    info->max_owned_nodes = P.max_owned;
+    info->n_tiles = P.tile_eb.empty() ? 0 : (int64_t)P.tile_eb.size() - 1;
+    info->halo_elements = (int64_t)P.halo.size();
+    info->step = c->step;
+    info->dt = P.dt;
+    info->dt_stable = c->dt_stable;
+    info->lambda_max = c->lambda_max;
+    const double w = (double)c->wsize, nq = (double)P.nq;
+    // algorithmic bytes: per element nq indices + 3 nq geometric factors + c2; per node
+    // dt/M plus read u, v and write u, v for every shot
+    info->alg_bytes_per_step = (double)P.ne * (nq * 4.0 + 3.0 * nq * w + w) +
+                               (double)P.nn * (w + 4.0 * w * c->S);
+    const double n = (double)P.n;
+    info->alg_flops_per_step = (double)P.ne * c->S * (8.0 * n * n * n + 7.0 * n * n) +
+                               (double)P.nn * c->S * 4.0;
+    info->setup_seconds = c->setup_seconds;
+    info->reorder_seconds = P.reorder_seconds;
+    return SEM_OK;
+}
+
+int sem_get_permutations(const sem_ctx* c, int32_t* e, int32_t* n) {
+    if (!c) return SEM_ERR_INVALID_ARG;
+    if (e) std::memcpy(e, c->plan.elem_new2old.data(), c->plan.ne * sizeof(int32_t));
+    if (n) std::memcpy(n, c->plan.node_new2old.data(), c->plan.nn * sizeof(int32_t));
+    return SEM_OK;
+}
+
+int sem_get_node_coords(const sem_ctx* c, double* xy) {
+    if (!c || !xy) return SEM_ERR_INVALID_ARG;
+    std::memcpy(xy, c->plan.node_xy.data(), c->plan.nn * 2 * sizeof(double));
+    return SEM_OK;
+}
+
+int sem_set_sources(sem_ctx* c, int32_t n, const double* xy, const int32_t* shot, double f0, double t0,
+                    int32_t* node_out) {
+    if (!c) return SEM_ERR_INVALID_ARG;
+    if (n < 0 || (n > 0 && (!xy || !shot))) return fail(c, SEM_ERR_INVALID_ARG, "bad source arrays");
+    for (int32_t i = 0; i < n; ++i)
+        if (shot[i] < 0 || shot[i] >= c->S) return fail(c, SEM_ERR_INVALID_ARG, "source shot out of range");
+    if (!(f0 > 0.0)) return fail(c, SEM_ERR_INVALID_ARG, "f0 must be positive");
+    if (c->plan.tile_eb.empty()) return fail(c, SEM_ERR_INVALID_ARG, "no tiling (node_order ORIGINAL)");
+    c->f0 = f0;
+    c->t0 = t0;
+    if (!c->host_only) { int rc = set_device(c); if (rc) return rc; }
+    return c->precision == SEM_F64 ? set_sources_t<double>(c, n, xy, shot, node_out)
+                                   : set_sources_t<float>(c, n, xy, shot, node_out);
+}
+
+int sem_set_receivers(sem_ctx* c, int32_t n, const double* xy, int32_t* node_out) {
+    if (!c) return SEM_ERR_INVALID_ARG;
+    if (n < 0 || (n > 0 && !xy)) return fail(c, SEM_ERR_INVALID_ARG, "bad receiver arrays");
+    if (c->plan.tile_eb.empty()) return fail(c, SEM_ERR_INVALID_ARG, "no tiling (node_order ORIGINAL)");
+    if (!c->host_only) { int rc = set_device(c); if (rc) return rc; }
+    return c->precision == SEM_F64 ? set_receivers_t<double>(c, n, xy, node_out)
+                                   : set_receivers_t<float>(c, n, xy, node_out);
+}
+
+int sem_set_c2(sem_ctx* c, const double* c2) {
+    if (!c || !c2) return SEM_ERR_INVALID_ARG;
+    for (int64_t e = 0; e < c->plan.ne; ++e)
+        if (!(c2[e] > 0.0) || !std::isfinite(c2[e])) return fail(c, SEM_ERR_INVALID_ARG, "c2 must be positive");
+    for (int64_t k = 0; k < c->plan.ne; ++k) c->plan.c2[k] = c2[c->plan.elem_new2old[k]];
+    if (c->host_only) return SEM_OK;
+    int rc = set_device(c);
+    if (rc) return rc;
+    SEM_HIP(c, upload_real(c, c->c2, c->plan.c2));
+    rc = c->precision == SEM_F64 ? power_iteration<double>(c, 60) : power_iteration<float>(c, 60);
+    if (rc) return rc;
+    if (!(c->plan.dt < c->dt_stable))
+        return fail(c, SEM_ERR_UNSTABLE_DT, "dt exceeds the stability limit of the new model");
+    return SEM_OK;
+}
+
+int sem_reset(sem_ctx* c) {
+    if (!c) return SEM_ERR_INVALID_ARG;
+    int rc = need_device(c);
+    if (rc) return rc;
+    rc = set_device(c);
+    if (rc) return rc;
+    return c->precision == SEM_F64 ? zero_state<double>(c) : zero_state<float>(c);
+}
+
+int sem_run(sem_ctx* c, int64_t nsteps, void* traces) {
+    if (!c) return SEM_ERR_INVALID_ARG;
+    if (nsteps < 0) return fail(c, SEM_ERR_INVALID_ARG, "nsteps must be >= 0");
+    int rc = need_device(c);
+    if (rc) return rc;
+    rc = set_device(c);
+    if (rc) return rc;
+    return c->precision == SEM_F64 ? run_t<double>(c, nsteps, traces) : run_t<float>(c, nsteps, traces);
+}
+
+int sem_step(sem_ctx* c) { return sem_run(c, 1, nullptr); }
+
+int sem_get_field(sem_ctx* c, int32_t which, void* dev) {
+    if (!c || !dev || (which != SEM_FIELD_U && which != SEM_FIELD_V)) return SEM_ERR_INVALID_ARG;
+    int rc = need_device(c);
+    if (rc) return rc;
+    rc = set_device(c);
+    if (rc) return rc;
+    const void* src = which == SEM_FIELD_U ? c->u[c->cur].p : c->v.p;
+    if (c->precision == SEM_F64)
+        SEM_HIP(c, sem::launch_nodes_to_original<double>((const double*)src, (double*)dev,
+                                                         (const int32_t*)c->n2o_node.p, c->plan.nn, c->S, c->stream));
+    else
+        SEM_HIP(c, sem::launch_nodes_to_original<float>((const float*)src, (float*)dev,
+                                                        (const int32_t*)c->n2o_node.p, c->plan.nn, c->S, c->stream));
+    return SEM_OK;
+}
+
+int sem_set_field(sem_ctx* c, int32_t which, const void* dev) {
+    if (!c || !dev || (which != SEM_FIELD_U && which != SEM_FIELD_V)) return SEM_ERR_INVALID_ARG;
+    int rc = need_device(c);
+    if (rc) return rc;
+    rc = set_device(c);
+    if (rc) return rc;
+    void* dst = which == SEM_FIELD_U ? c->u[c->cur].p : c->v.p;
+    if (c->precision == SEM_F64)
+        SEM_HIP(c, sem::launch_nodes_from_original<double>((const double*)dev, (double*)dst,
+                                                           (const int32_t*)c->n2o_node.p, c->plan.nn, c->S, c->stream));
+    else
+        SEM_HIP(c, sem::launch_nodes_from_original<float>((const float*)dev, (float*)dst,
+                                                          (const int32_t*)c->n2o_node.p, c->plan.nn, c->S, c->stream));
+    return SEM_OK;
+}
+
+int sem_apply_stiffness(sem_ctx* c, const void* u_dev, void* r_dev) {
+    if (!c || !u_dev || !r_dev) return SEM_ERR_INVALID_ARG;
+    int rc = need_device(c);
+    if (rc) return rc;
+    rc = set_device(c);
+    if (rc) return rc;
+    return c->precision == SEM_F64 ? apply_t<double>(c, u_dev, r_dev) : apply_t<float>(c, u_dev, r_dev);
+}
+
+int sem_adjoint_gradient(sem_ctx* c, const void* dL, int64_t nsteps, int32_t ckpt_every, double* grad) {
+    if (!c || !dL || !grad) return SEM_ERR_INVALID_ARG;
+    if (nsteps < 1 || ckpt_every < 1) return fail(c, SEM_ERR_INVALID_ARG, "nsteps and ckpt_every must be >= 1");
+    int rc = need_device(c);
+    if (rc) return rc;
+    rc = set_device(c);
+    if (rc) return rc;
+    if (c->n_rec < 1) return fail(c, SEM_ERR_INVALID_ARG, "no receivers set");
+    return c->precision == SEM_F64 ? adjoint_t<double>(c, dL, nsteps, ckpt_every, grad)
+                                   : adjoint_t<float>(c, dL, nsteps, ckpt_every, grad);
+}
+
+int sem_synchronize(sem_ctx* c) {
+    if (!c) return SEM_ERR_INVALID_ARG;
+    if (c->host_only) return SEM_OK;
+    int rc = set_device(c);
+    if (rc) return rc;
+    SEM_HIP(c, hipStreamSynchronize(c->stream));
+    return SEM_OK;
+}
+
+int sem_hilbert_index(int64_t W, int64_t H, int64_t n, const int64_t* cx, const int64_t* cy, int64_t* out) {
+    if (W < 1 || H < 1 || n < 0 || (n > 0 && (!cx || !cy || !out))) return SEM_ERR_INVALID_ARG;
+    for (int64_t i = 0; i < n; ++i) {
+        if (cx[i] < 0 || cx[i] >= W || cy[i] < 0 || cy[i] >= H) return SEM_ERR_INVALID_ARG;
+        out[i] = sem::hilbert_index(W, H, cx[i], cy[i]);
+    }
+    return SEM_OK;
+}
+
+const char* sem_last_error(const sem_ctx* c) {
+    if (!c) return "null context";
+    return c->err.c_str();
+}
+
+void sem_destroy(sem_ctx* c) {
+    if (!c) return;
+    if (!c->host_only) {
+        hipSetDevice(c->device);
+        hipStreamSynchronize(c->stream);
+        DevBuf* bufs[] = {&c->conn, &c->G, &c->c2, &c->dtminv, &c->tile_eb, &c->tile_nb, &c->halo_b,
+                          &c->halo, &c->n2o_node, &c->n2o_elem, &c->u[0], &c->u[1], &c->v,
+                          &c->src_b, &c->src_loc, &c->src_shot, &c->src_w, &c->rec_b, &c->rec_loc,
+                          &c->rec_idx};
+        for (DevBuf* b : bufs) dev_free(*b);
+    }
+    delete c;
+}
+
+}  // extern "C"

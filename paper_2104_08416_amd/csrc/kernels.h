@@ -1,0 +1,84 @@
+// kernels.h -- launch interface of the gfx950 kernels (internal to the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace sem {
+
+constexpr int kBlock = 256;     // threads per workgroup of every kernel
+constexpr int kMaxP = 7;
+
+// Arguments of the fused step kernel. All arrays use the new (curve) numbering.
+template <typename T>
+struct StepArgs {
+    // mesh
+    const int32_t* conn;      // [E/64][nq][64] global node of local node q of element e
+    const T* G;               // [E/64][3][nq][64] geometric factors (11, 12, 22)
+    const T* c2;              // [E]
+    const T* dtminv;          // [N] dt / lumped mass
+    int64_t E;
+    int32_t S;                // shots (row length of the [N][S] state)
+    // byte sizes of the buffers read through bounds-checked buffer loads (each < 4 GiB)
+    uint32_t conn_bytes, G_bytes, c2_bytes, state_bytes;
+    // tiling
+    const int32_t* tile_eb;   // [T+1] element range of each tile
+    const int32_t* tile_nb;   // [T+1] owned node range of each tile
+    const int32_t* halo_b;    // [T+1]
+    const int32_t* halo;      // halo elements of all tiles
+    int32_t n_slices;         // S / shot_lanes
+    // state: reads u_in, writes u_out, updates v in place
+    const T* u_in;
+    T* u_out;
+    T* v;
+    T dt;
+    int32_t mode;             // 0 step, 1 r_out = K u_in, 2 r_out = dt M^-1 K u_in
+    T* r_out;
+    // point sources: per-tile CSR of (owned-local node, shot, weight)
+    const int32_t* src_b;
+    const int32_t* src_loc;
+    const int32_t* src_shot;
+    const T* src_w;
+    double src_t, f0, t0;
+    // receivers: per-tile CSR of (owned-local node, receiver index)
+    const int32_t* rec_b;
+    const int32_t* rec_loc;
+    const int32_t* rec_idx;
+    int32_t n_rec;
+    T* trace;                 // record u after the step: [S][n_rec][trace_cols] (+ col)
+    int64_t trace_cols, trace_col;
+    const T* inj;             // inject at receivers: inj[s][r][inj_cols] (col) * inj_scale
+    int64_t inj_cols, inj_col;
+    T inj_scale;
+    // gradient pairing: grad[e] += sum_s (Khat_e u_in_e) . (u_pair_e)
+    const T* u_pair;
+    double* grad;
+    // 1D derivative matrix D[i*(p+1) + j] = l_j'(xi_i)
+    T D[(kMaxP + 1) * (kMaxP + 1)];
+};
+
+template <typename T>
+hipError_t launch_step(int p, int shot_lanes, int64_t n_tiles, size_t lds_bytes,
+                       const StepArgs<T>& a, hipStream_t stream);
+
+// out[s][old] = in[new][s]  (new -> old node map)
+template <typename T>
+hipError_t launch_nodes_to_original(const T* in, T* out, const int32_t* node_new2old, int64_t N,
+                                    int32_t S, hipStream_t stream);
+// out[new][s] = in[s][old]
+template <typename T>
+hipError_t launch_nodes_from_original(const T* in, T* out, const int32_t* node_new2old, int64_t N,
+                                      int32_t S, hipStream_t stream);
+template <typename T>
+hipError_t launch_fill(T* x, T value, int64_t n, hipStream_t stream);
+template <typename T>
+hipError_t launch_scale(T* x, double s, int64_t n, hipStream_t stream);
+// *out += sum x^2 (out must be zeroed first)
+template <typename T>
+hipError_t launch_sumsq(const T* x, int64_t n, double* out, hipStream_t stream);
+// out[elem_new2old[k]] = scale * acc[k]
+hipError_t launch_grad_to_original(const double* acc, double* out, const int32_t* elem_new2old,
+                                   int64_t E, double scale, hipStream_t stream);
+
+}  // namespace sem

@@ -1,0 +1,406 @@
+// kernels.hip -- gfx950 kernels of the Hilbert-ordered SEM time step.
+//
+// One fused launch per time step. Workgroup = one tile of consecutive elements in curve
+// order x one slice of `SL` shots. The tile owns the contiguous range of global nodes its
+// elements touch first (first-touch numbering makes it contiguous). The workgroup
+//   1. zeroes an LDS accumulator for its owned nodes,
+//   2. for every own element and every halo element (an element of another tile that
+//      touches an owned node): gathers u at the element's (p+1)^2 nodes, applies the
+//      tensor-product stiffness (D along each reference axis, geometric factors, D^T;
+//      Eqs. deriv_u and R of the paper in second-order form) and adds the contributions
+//      that land on owned nodes into LDS,
+//   3. subtracts point-source terms (Alg. 3) or adjoint injections,
+//   4. applies the diagonal-mass-inverse leapfrog update to its owned nodes:
+//      v += dt M^-1 (f - K u), u_out = u_in + dt v,
+//   5. records receivers it owns.
+// Halo recomputation replaces the paper's element colouring: every contribution to a
+// node is summed in its owner's LDS, so no global atomics and no second pass are needed,
+// and u is double-buffered (u_in -> u_out) so tiles never read a value updated in the
+// same launch.
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+
+// minimum waves per SIMD the register allocation must allow (FP32, FP64)
+#ifndef SEM_MIN_WAVES_F32
+#define SEM_MIN_WAVES_F32 3
+#endif
+#ifndef SEM_MIN_WAVES_F64
+#define SEM_MIN_WAVES_F64 1
+#endif
+
+namespace sem {
+namespace {
+
+__device__ __forceinline__ double ricker(double t, double f0, double t0) {
+    const double x = 3.14159265358979323846 * f0 * (t - t0);
+    const double a = x * x;
+    return (1.0 - 2.0 * a) * exp(-a);
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a contiguous run
+// of logical block ids so that curve-neighbouring tiles share that XCD's L2.
+__device__ __forceinline__ int xcd_logical_block() {
+    const int b = blockIdx.x, nblk = gridDim.x;
+    const int q8 = nblk >> 3, r8 = nblk & 7, x = b & 7;
+    return x * q8 + min(x, r8) + (b >> 3);
+}
+
+// Raw buffer loads: 128-bit descriptor in SGPRs, 32-bit byte offset in one VGPR, and
+// reads past the descriptor's byte count return 0 instead of touching other memory.
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+
+__device__ __forceinline__ rsrc_t make_rsrc(const void* p, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+
+template <typename T>
+__device__ __forceinline__ T bload(rsrc_t r, uint32_t off);
+template <>
+__device__ __forceinline__ float bload<float>(rsrc_t r, uint32_t off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+template <>
+__device__ __forceinline__ double bload<double>(rsrc_t r, uint32_t off) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+template <>
+__device__ __forceinline__ int bload<int>(rsrc_t r, uint32_t off) {
+    return (int)__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+}
+
+// Scheduling fence: the machine scheduler may not move instructions across it, so loads
+// of one stage are not hoisted into the previous one (bounds the registers live at once).
+__device__ __forceinline__ void stage_fence() { __builtin_amdgcn_sched_barrier(0); }
+
+template <int SL, typename T>
+__device__ __forceinline__ T group_sum(T v) {
+#pragma unroll
+    for (int m = 1; m < SL; m <<= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+template <typename T, int P, int SL>
+__global__ void __launch_bounds__(kBlock, sizeof(T) == 8 ? SEM_MIN_WAVES_F64 : SEM_MIN_WAVES_F32) step_kernel(const StepArgs<T> a) {
+    constexpr int N = P + 1, NQ = N * N;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* acc = reinterpret_cast<T*>(smem_raw);
+
+    const int logical = xcd_logical_block();
+    const int tile = logical / a.n_slices;
+    const int s0 = (logical - tile * a.n_slices) * SL;
+    const int nb = a.tile_nb[tile];
+    const int nown = a.tile_nb[tile + 1] - nb;
+    const int eb = a.tile_eb[tile];
+    const int n_own_el = a.tile_eb[tile + 1] - eb;
+    const int hb = a.halo_b[tile];
+    const int n_halo = a.halo_b[tile + 1] - hb;
+    const int S = a.S;
+
+    const rsrc_t r_conn = make_rsrc(a.conn, a.conn_bytes);
+    const rsrc_t r_G = make_rsrc(a.G, a.G_bytes);
+    const rsrc_t r_c2 = make_rsrc(a.c2, a.c2_bytes);
+    const rsrc_t r_u = make_rsrc(a.u_in, a.state_bytes);
+    const rsrc_t r_pair = make_rsrc(a.u_pair, a.u_pair ? a.state_bytes : 0u);
+    const uint32_t ustride = (uint32_t)S * (uint32_t)sizeof(T);
+
+    for (int i = threadIdx.x; i < nown * SL; i += kBlock) acc[i] = T(0);
+    __syncthreads();
+
+    const int n_items = (n_own_el + n_halo) * SL;
+    for (int item = threadIdx.x; item < n_items; item += kBlock) {
+        const int k = item / SL;
+        const int s = item - k * SL;
+        const bool own = k < n_own_el;
+        const int e = own ? eb + k : a.halo[hb + k - n_own_el];
+        // element-blocked layouts: [E/64][component][q][64]; one byte offset per thread
+        const uint32_t eoff = (uint32_t)((e >> 6) * (NQ * 64) + (e & 63)) * 4u;
+        const uint32_t goff = (uint32_t)((e >> 6) * (3 * NQ * 64) + (e & 63)) * (uint32_t)sizeof(T);
+        const uint32_t soff = (uint32_t)(s0 + s) * (uint32_t)sizeof(T);
+        T u[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int node = bload<int>(r_conn, eoff + q * 256);
+            u[q] = bload<T>(r_u, (uint32_t)node * ustride + soff);
+        }
+        stage_fence();
+        // Row by row (second reference index j): reference gradient at the row's GLL
+        // points, geometric flux, then both D^T contractions folded in at once:
+        //   r[a, j] += sum_i D[i, a] f1[i, j]   (first-axis flux of row j is complete)
+        //   r[a, b] += D[j, b] f2[a, j]          (second-axis flux summed over rows)
+        // so only u, r and one row of flux are live.
+        T r[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) r[q] = T(0);
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            T f1[N], f2[N];
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                T gx = T(0), gy = T(0);
+#pragma unroll
+                for (int m = 0; m < N; ++m) {
+                    gx += a.D[i * N + m] * u[m + N * j];
+                    gy += a.D[j * N + m] * u[i + N * m];
+                }
+                const int q = i + N * j;
+                const T g11 = bload<T>(r_G, goff + q * 64 * (uint32_t)sizeof(T));
+                const T g12 = bload<T>(r_G, goff + (NQ + q) * 64 * (uint32_t)sizeof(T));
+                const T g22 = bload<T>(r_G, goff + (2 * NQ + q) * 64 * (uint32_t)sizeof(T));
+                f1[i] = g11 * gx + g12 * gy;
+                f2[i] = g12 * gx + g22 * gy;
+            }
+#pragma unroll
+            for (int aa = 0; aa < N; ++aa) {
+                T acc1 = r[aa + N * j];
+#pragma unroll
+                for (int i = 0; i < N; ++i) acc1 += a.D[i * N + aa] * f1[i];
+                r[aa + N * j] = acc1;
+            }
+#pragma unroll
+            for (int bb = 0; bb < N; ++bb) {
+#pragma unroll
+                for (int aa = 0; aa < N; ++aa) r[aa + N * bb] += a.D[j * N + bb] * f2[aa];
+            }
+            stage_fence();
+        }
+        const T c2 = bload<T>(r_c2, (uint32_t)e * (uint32_t)sizeof(T));
+        const bool pair = own && a.grad != nullptr;
+        T dot = T(0);
+        // scatter the owned entries into LDS. The node ids are re-read here (cache hits)
+        // rather than kept live through the contraction.
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int node = bload<int>(r_conn, eoff + q * 256);
+            if (pair) dot += r[q] * bload<T>(r_pair, (uint32_t)node * ustride + soff);
+            const int loc = node - nb;
+            if ((unsigned)loc < (unsigned)nown) atomicAdd(&acc[loc * SL + s], c2 * r[q]);
+        }
+        if (a.grad != nullptr) {
+            // every lane of an SL-group is active together (items are SL-aligned)
+            dot = group_sum<SL>(dot);
+            if (pair && s == 0) atomicAdd(&a.grad[e], (double)dot);
+        }
+    }
+    __syncthreads();
+
+    // point sources of this tile: acc -= w * ricker(t)
+    if (a.src_b != nullptr) {
+        const int sb = a.src_b[tile], se = a.src_b[tile + 1];
+        if (se > sb) {
+            const T amp = (T)ricker(a.src_t, a.f0, a.t0);
+            for (int i = sb + threadIdx.x; i < se; i += kBlock) {
+                const int sh = a.src_shot[i] - s0;
+                if ((unsigned)sh < (unsigned)SL) atomicAdd(&acc[a.src_loc[i] * SL + sh], -a.src_w[i] * amp);
+            }
+            __syncthreads();
+        }
+    }
+    // adjoint injection at receivers: acc -= inj[s][r][col] * scale
+    if (a.inj != nullptr) {
+        const int rb = a.rec_b[tile], re = a.rec_b[tile + 1];
+        if (re > rb) {
+            for (int i = threadIdx.x; i < (re - rb) * SL; i += kBlock) {
+                const int k = rb + i / SL, s = i % SL;
+                const T val = a.inj[((int64_t)(s0 + s) * a.n_rec + a.rec_idx[k]) * a.inj_cols + a.inj_col];
+                atomicAdd(&acc[a.rec_loc[k] * SL + s], -val * a.inj_scale);
+            }
+            __syncthreads();
+        }
+    }
+
+    if (a.mode == 0) {
+        for (int i = threadIdx.x; i < nown * SL; i += kBlock) {
+            const int loc = i / SL, s = i - (i / SL) * SL;
+            const int node = nb + loc;
+            const int64_t g = (int64_t)node * S + s0 + s;
+            const T vn = a.v[g] - a.dtminv[node] * acc[i];
+            a.v[g] = vn;
+            const T un = a.u_in[g] + a.dt * vn;
+            a.u_out[g] = un;
+            acc[i] = un;
+        }
+        if (a.trace != nullptr) {
+            const int rb = a.rec_b[tile], re = a.rec_b[tile + 1];
+            if (re > rb) {
+                __syncthreads();
+                for (int i = threadIdx.x; i < (re - rb) * SL; i += kBlock) {
+                    const int k = rb + i / SL, s = i % SL;
+                    a.trace[((int64_t)(s0 + s) * a.n_rec + a.rec_idx[k]) * a.trace_cols + a.trace_col] =
+                        acc[a.rec_loc[k] * SL + s];
+                }
+            }
+        }
+    } else {
+        for (int i = threadIdx.x; i < nown * SL; i += kBlock) {
+            const int loc = i / SL, s = i - (i / SL) * SL;
+            const int node = nb + loc;
+            const int64_t g = (int64_t)node * S + s0 + s;
+            a.r_out[g] = a.mode == 2 ? a.dtminv[node] * acc[i] : acc[i];
+        }
+    }
+}
+
+template <typename T, int P, int SL>
+hipError_t launch_one(int64_t n_tiles, size_t lds, const StepArgs<T>& a, hipStream_t st) {
+    auto fn = step_kernel<T, P, SL>;
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    const int64_t blocks = n_tiles * a.n_slices;
+    hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(kBlock), lds, st, a);
+    return hipGetLastError();
+}
+
+template <typename T, int P>
+hipError_t launch_p(int sl, int64_t nt, size_t lds, const StepArgs<T>& a, hipStream_t st) {
+    switch (sl) {
+        case 1: return launch_one<T, P, 1>(nt, lds, a, st);
+        case 2: return launch_one<T, P, 2>(nt, lds, a, st);
+        case 4: return launch_one<T, P, 4>(nt, lds, a, st);
+        case 8: return launch_one<T, P, 8>(nt, lds, a, st);
+        case 16: return launch_one<T, P, 16>(nt, lds, a, st);
+        case 32: return launch_one<T, P, 32>(nt, lds, a, st);
+        case 64: return launch_one<T, P, 64>(nt, lds, a, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// ------------------------------------------------------------------ utility kernels
+template <typename T>
+__global__ void to_original_kernel(const T* in, T* out, const int32_t* n2o, int64_t N, int32_t S) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N * S) return;
+    const int64_t node = i / S;
+    const int s = (int)(i - node * S);
+    out[(int64_t)s * N + n2o[node]] = in[i];
+}
+
+template <typename T>
+__global__ void from_original_kernel(const T* in, T* out, const int32_t* n2o, int64_t N, int32_t S) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N * S) return;
+    const int64_t node = i / S;
+    const int s = (int)(i - node * S);
+    out[i] = in[(int64_t)s * N + n2o[node]];
+}
+
+template <typename T>
+__global__ void fill_kernel(T* x, T v, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        x[i] = v;
+}
+
+template <typename T>
+__global__ void scale_kernel(T* x, double s, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        x[i] = (T)((double)x[i] * s);
+}
+
+template <typename T>
+__global__ void sumsq_kernel(const T* x, int64_t n, double* out) {
+    __shared__ double part[kBlock / 64];
+    double s = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double v = (double)x[i];
+        s += v * v;
+    }
+    for (int m = 32; m >= 1; m >>= 1) s += __shfl_xor(s, m, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < kBlock / 64; ++w) t += part[w];
+        atomicAdd(out, t);
+    }
+}
+
+__global__ void grad_to_original_kernel(const double* acc, double* out, const int32_t* e2o, int64_t E,
+                                        double scale) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < E) out[e2o[k]] = scale * acc[k];
+}
+
+inline unsigned grid_for(int64_t n) {
+    const int64_t b = (n + kBlock - 1) / kBlock;
+    return (unsigned)(b < 1 ? 1 : b);
+}
+
+inline unsigned grid_stride(int64_t n) {
+    const int64_t b = (n + kBlock - 1) / kBlock;
+    return (unsigned)(b < 1 ? 1 : (b > 8192 ? 8192 : b));
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_step(int p, int sl, int64_t nt, size_t lds, const StepArgs<T>& a, hipStream_t st) {
+    switch (p) {
+        case 1: return launch_p<T, 1>(sl, nt, lds, a, st);
+        case 2: return launch_p<T, 2>(sl, nt, lds, a, st);
+        case 3: return launch_p<T, 3>(sl, nt, lds, a, st);
+        case 4: return launch_p<T, 4>(sl, nt, lds, a, st);
+        case 5: return launch_p<T, 5>(sl, nt, lds, a, st);
+        case 6: return launch_p<T, 6>(sl, nt, lds, a, st);
+        case 7: return launch_p<T, 7>(sl, nt, lds, a, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+hipError_t launch_nodes_to_original(const T* in, T* out, const int32_t* n2o, int64_t N, int32_t S,
+                                    hipStream_t st) {
+    hipLaunchKernelGGL(to_original_kernel<T>, dim3(grid_for(N * S)), dim3(kBlock), 0, st, in, out, n2o, N, S);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_nodes_from_original(const T* in, T* out, const int32_t* n2o, int64_t N, int32_t S,
+                                      hipStream_t st) {
+    hipLaunchKernelGGL(from_original_kernel<T>, dim3(grid_for(N * S)), dim3(kBlock), 0, st, in, out, n2o, N, S);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fill(T* x, T v, int64_t n, hipStream_t st) {
+    hipLaunchKernelGGL(fill_kernel<T>, dim3(grid_stride(n)), dim3(kBlock), 0, st, x, v, n);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_scale(T* x, double s, int64_t n, hipStream_t st) {
+    hipLaunchKernelGGL(scale_kernel<T>, dim3(grid_stride(n)), dim3(kBlock), 0, st, x, s, n);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_sumsq(const T* x, int64_t n, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(sumsq_kernel<T>, dim3(grid_stride(n)), dim3(kBlock), 0, st, x, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad_to_original(const double* acc, double* out, const int32_t* e2o, int64_t E,
+                                   double scale, hipStream_t st) {
+    hipLaunchKernelGGL(grad_to_original_kernel, dim3(grid_for(E)), dim3(kBlock), 0, st, acc, out, e2o, E, scale);
+    return hipGetLastError();
+}
+
+#define SEM_INSTANTIATE(T)                                                                        \
+    template hipError_t launch_step<T>(int, int, int64_t, size_t, const StepArgs<T>&, hipStream_t); \
+    template hipError_t launch_nodes_to_original<T>(const T*, T*, const int32_t*, int64_t, int32_t,   \
+                                                    hipStream_t);                                 \
+    template hipError_t launch_nodes_from_original<T>(const T*, T*, const int32_t*, int64_t,        \
+                                                      int32_t, hipStream_t);                      \
+    template hipError_t launch_fill<T>(T*, T, int64_t, hipStream_t);                              \
+    template hipError_t launch_scale<T>(T*, double, int64_t, hipStream_t);                        \
+    template hipError_t launch_sumsq<T>(const T*, int64_t, double*, hipStream_t);
+
+SEM_INSTANTIATE(float)
+SEM_INSTANTIATE(double)
+
+}  // namespace sem

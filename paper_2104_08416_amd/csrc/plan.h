@@ -1,0 +1,73 @@
+// plan.h -- host-side setup of the Hilbert-ordered SEM step (internal to the library).
+//
+// The plan holds everything the device step needs, in the NEW (curve) numbering:
+// element-major structure-of-arrays connectivity and geometric factors, the lumped
+// mass, the workgroup tiling with each tile's owned node range and halo elements, and
+// the permutations back to the original numbering.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace sem {
+
+struct MeshIn {
+    int64_t nv = 0, ne = 0;
+    const double* vxy = nullptr;
+    const int32_t* quad = nullptr;
+    const double* c2 = nullptr;
+};
+
+struct PlanOptions {
+    int p = 4;
+    int elem_order = 0;      // 0 hilbert, 1 morton, 2 lex, 3 random
+    int node_order = 0;      // 0 first touch + degree, 1 original
+    uint64_t seed = 3;
+    double dt = 0.0;
+    double cfl = 0.3;
+    int tile_elems = 128;
+};
+
+struct Plan {
+    int p = 0, n = 0, nq = 0;
+    int64_t ne = 0, nn = 0, nv = 0;
+    double dt = 0.0;
+    // 1D GLL ingredients
+    std::vector<double> xi, w, D;            // D[i*n + j] = l_j'(xi_i)
+    // original numbering
+    std::vector<int32_t> conn0;              // [ne][nq] original node ids
+    std::vector<double> node_xy;             // [nn][2] original numbering
+    // permutations
+    std::vector<int32_t> elem_new2old, elem_old2new;
+    std::vector<int32_t> node_new2old, node_old2new;
+    // device-bound arrays, new numbering
+    std::vector<int32_t> conn_soa;           // [nq][ne] new node ids
+    std::vector<double> G_soa;               // [3][nq][ne] w_a w_b detJ J^-1 J^-T (11, 12, 22)
+    std::vector<double> c2;                  // [ne]
+    std::vector<double> minv;                // [nn] 1 / lumped mass
+    // tiling (new numbering): tile t has elements [tile_eb[t], tile_eb[t+1]), owns nodes
+    // [tile_nb[t], tile_nb[t+1]), and recomputes halo[halo_b[t] .. halo_b[t+1]).
+    int tile_elems = 0;
+    std::vector<int32_t> tile_eb, tile_nb, halo_b, halo;
+    int32_t max_owned = 0;
+    double reorder_seconds = 0.0;
+};
+
+// Fills `plan` or returns a non-empty error string; `code` receives the sem_status.
+std::string build_plan(const MeshIn& mesh, const PlanOptions& opt, Plan& plan, int& code);
+
+// Rebuild the tiling of an existing plan for another tile size.
+void build_tiles(Plan& plan, int tile_elems);
+
+// Cell index along the generalized Hilbert curve over a W x H grid.
+int64_t hilbert_index(int64_t W, int64_t H, int64_t cx, int64_t cy);
+
+// Nearest global node (original numbering) of a point; ties -> lowest id.
+int32_t nearest_node(const Plan& plan, double x, double y);
+
+// Geometric factors of one element (original numbering) at its (p+1)^2 GLL points.
+void element_geometry(const Plan& plan, const MeshIn& mesh, int64_t e, double* g11, double* g12,
+                      double* g22, double* det);
+
+}  // namespace sem

@@ -20,3 +20,14 @@ def gpu_ok():
     if not torch.cuda.is_available():
         pytest.fail("GPU test collected on a machine without a GPU")
     return True
+
+
+@pytest.fixture(scope="session")
+def semlib():
+    """The ctypes binding; builds the library first if it is not built yet."""
+    lib = os.path.join(ROOT, "paper_2104_08416_amd", "libsem_hip.so")
+    if not os.path.exists(lib):
+        from paper_2104_08416_amd import build
+        build.build()
+    from paper_2104_08416_amd import sem
+    return sem

@@ -1,0 +1,200 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Tolerances: FP64 paths rel L2 <= 1e-12 (rounding order only); FP32 after 1000 steps
+rel L2 <= 1e-5; gradients vs central finite differences <= 1e-4.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import adjoint, mesh, solver
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def run_both(semlib, wl, nsteps, precision="f64", order="hilbert", **kw):
+    o = solver.SEM(wl.vxy, wl.quads, wl.c2, wl.p)
+    dt = o.dt_cfl()
+    src = solver.snap_to_nodes(wl.src_xy, o.node_xy)
+    rec = solver.snap_to_nodes(wl.rec_xy, o.node_xy)
+    tr_o, u_o, v_o = o.run(nsteps, dt, src, wl.src_shot, wl.f0, rec_nodes=rec, n_shots=wl.n_shots)
+    s = semlib.Simulator(wl.vxy, wl.quads, wl.c2, wl.p, precision=precision, order=order,
+                         n_shots=wl.n_shots, dt=dt, **kw)
+    gsrc = s.set_sources(wl.src_xy, wl.src_shot, wl.f0)
+    grec = s.set_receivers(wl.rec_xy)
+    np.testing.assert_array_equal(gsrc, src)
+    np.testing.assert_array_equal(grec, rec)
+    tr = s.run(nsteps)
+    u = s.get_field(semlib.FIELD_U)
+    v = s.get_field(semlib.FIELD_V)
+    s.synchronize()
+    out = (tr.cpu().numpy(), u.cpu().numpy().T, v.cpu().numpy().T)
+    s.close()
+    return out, (tr_o, u_o, v_o)
+
+
+@pytest.mark.parametrize("order", ["hilbert", "lex", "random"])
+def test_fp64_homog64_full_size(semlib, gpu_ok, order):
+    """64 x 64 uniform quads, p=4, c=1500, Ricker 10 Hz at the centre, 200 steps, FP64."""
+    say("case homog64 fp64", order)
+    wl = workloads.workload("homog64")
+    (tr, u, v), (tr_o, u_o, v_o) = run_both(semlib, wl, wl.nsteps, "f64", order)
+    assert np.abs(u_o).max() > 0
+    assert rel(u, u_o) <= 1e-12
+    assert rel(v, v_o) <= 1e-12
+    assert np.abs(tr - tr_o).max() <= 1e-12 * np.abs(u_o).max()
+
+
+@pytest.mark.parametrize("order", ["hilbert", "morton", "lex", "random"])
+def test_fp64_layered_ragged_tiles(semlib, gpu_ok, order):
+    """30 x 30 jittered layered mesh with 64-element tiles: 15 tiles, a ragged last tile,
+    halos across tile borders; source close enough that receivers see the wave."""
+    say("case layered30 fp64", order)
+    wl = workloads.workload("layered1024", n=30, nsteps=400)
+    wl.src_xy = np.array([[5000.0, 8000.0]])
+    (tr, u, v), (tr_o, u_o, v_o) = run_both(semlib, wl, wl.nsteps, "f64", order, tile_elems=64)
+    assert rel(u, u_o) <= 1e-12
+    assert rel(tr, tr_o) <= 1e-12
+
+
+@pytest.mark.parametrize("lanes", [1, 2, 8])
+def test_fp64_batched_shots(semlib, gpu_ok, lanes):
+    """8 shots at seeded positions advanced together, shots-per-element lanes 1/2/8."""
+    say("case batch fp64 lanes", lanes)
+    wl = workloads.workload("batch512", n=24, n_shots=8, nsteps=300)
+    (tr, u, v), (tr_o, u_o, v_o) = run_both(semlib, wl, wl.nsteps, "f64", "hilbert",
+                                            shot_lanes=lanes, tile_elems=48)
+    assert rel(u, u_o) <= 1e-12
+    assert rel(tr, tr_o) <= 1e-12
+
+
+def test_fp32_1000_steps(semlib, gpu_ok):
+    """FP32 state and arithmetic against the FP64 oracle after 1000 steps."""
+    say("case layered64 fp32 1000 steps")
+    wl = workloads.workload("layered1024", n=64, nsteps=1000)
+    (tr, u, v), (tr_o, u_o, v_o) = run_both(semlib, wl, wl.nsteps, "f32", "hilbert")
+    err = rel(u, u_o)
+    say("fp32 rel L2 after 1000 steps", err)
+    assert err <= 1e-5
+
+
+def test_apply_stiffness_fp64(semlib, gpu_ok):
+    import torch
+    say("case apply fp64")
+    wl = workloads.workload("layered1024", n=40)
+    o = solver.SEM(wl.vxy, wl.quads, wl.c2, wl.p)
+    s = semlib.Simulator(wl.vxy, wl.quads, wl.c2, wl.p, precision="f64", n_shots=2, tile_elems=100)
+    x = workloads.random_field(o.n_nodes, 2, seed=3)
+    r = s.apply_stiffness(torch.tensor(x, device="cuda")).cpu().numpy()
+    r_o = (o.K @ x.T).T
+    assert rel(r, r_o) <= 1e-13
+
+
+def test_resume_from_saved_fields(semlib, gpu_ok):
+    """run(200) == run(100) + save (u, v) + restore into a fresh context + run(100)."""
+    import torch
+    say("case resume")
+    wl = workloads.workload("layered1024", n=20)
+    o = solver.SEM(wl.vxy, wl.quads, wl.c2, wl.p)
+    u0 = np.exp(-((o.node_xy[:, 0] - 4000) ** 2 + (o.node_xy[:, 1] - 6000) ** 2) / 2e6)[None, :]
+    a = semlib.Simulator(wl.vxy, wl.quads, wl.c2, wl.p, precision="f64")
+    a.set_field(semlib.FIELD_U, torch.tensor(u0, device="cuda"))
+    a.run(100, record=False)
+    su, sv = a.get_field(semlib.FIELD_U), a.get_field(semlib.FIELD_V)
+    a.run(100, record=False)
+    ua = a.get_field(semlib.FIELD_U).cpu().numpy()
+    b = semlib.Simulator(wl.vxy, wl.quads, wl.c2, wl.p, precision="f64")
+    b.set_field(semlib.FIELD_U, su)
+    b.set_field(semlib.FIELD_V, sv)
+    b.run(100, record=False)
+    ub = b.get_field(semlib.FIELD_U).cpu().numpy()
+    assert rel(ub, ua) <= 1e-14
+    _, u_o, _ = o.run(200, a.dt, u0=u0.T)
+    assert rel(ua, u_o.T) <= 1e-12
+
+
+def _tiny_inversion(semlib, precision, shots=2, nsteps=80, n=8, p=3):
+    vxy, quads, xc, yc = workloads.grid_mesh(n, n, 800.0, 800.0, jitter=0.2, seed=9)
+    c = workloads.layered_c(yc, 800.0, c_top=1500.0, c_step=300.0)
+    rng = np.random.default_rng(21)
+    c2_true = (c * (1 + 0.1 * rng.uniform(-1, 1, c.size))) ** 2
+    c2 = c * c
+    o = solver.SEM(vxy, quads, c2_true, p)
+    dt = o.dt_cfl()
+    src_xy = np.array([[200.0, 600.0], [560.0, 400.0]])[:shots]
+    rec_xy = np.stack([np.linspace(50, 750, 9), np.full(9, 800.0)], 1)
+    src = solver.snap_to_nodes(src_xy, o.node_xy)
+    rec = solver.snap_to_nodes(rec_xy, o.node_xy)
+    f0 = 30.0
+    obs, _, _ = o.run(nsteps, dt, src, np.arange(shots), f0, rec_nodes=rec, n_shots=shots)
+    o.set_c2(c2)
+    J, g_o = adjoint.misfit_and_gradient(o, nsteps, dt, src, np.arange(shots), f0, rec, shots, obs)
+    s = semlib.Simulator(vxy, quads, c2, p, precision=precision, n_shots=shots, dt=dt, tile_elems=16)
+    s.set_sources(src_xy, np.arange(shots), f0)
+    s.set_receivers(rec_xy)
+    return o, s, dict(dt=dt, src=src, rec=rec, f0=f0, obs=obs, J=J, g=g_o, c2=c2, nsteps=nsteps,
+                      shots=shots)
+
+
+@pytest.mark.parametrize("ckpt", [7, 80, 200])
+def test_adjoint_gradient_fp64_matches_oracle(semlib, gpu_ok, ckpt):
+    import torch
+    say("case adjoint fp64 ckpt", ckpt)
+    o, s, d = _tiny_inversion(semlib, "f64")
+    tr = s.run(d["nsteps"])
+    res = tr - torch.tensor(d["obs"], device="cuda")
+    J = 0.5 * float((res.double() ** 2).sum())
+    assert J == pytest.approx(d["J"], rel=1e-11)
+    g = s.adjoint_gradient(res.contiguous(), d["nsteps"], ckpt).cpu().numpy()
+    assert rel(g, d["g"]) <= 1e-10
+
+
+def test_adjoint_gradient_fp32_vs_finite_differences(semlib, gpu_ok):
+    import torch
+    say("case adjoint fp32 vs FD")
+    o, s, d = _tiny_inversion(semlib, "f32", nsteps=120)
+    tr = s.run(d["nsteps"])
+    res = (tr.double() - torch.tensor(d["obs"], device="cuda")).float().contiguous()
+    g = s.adjoint_gradient(res, d["nsteps"], 40).cpu().numpy()
+    rng = np.random.default_rng(4)
+    els = rng.choice(d["c2"].size, 16, replace=False)
+    fd = []
+    for e in els:
+        h = 1e-4 * d["c2"][e]
+        Js = []
+        for sgn in (1, -1):
+            cp = d["c2"].copy()
+            cp[e] += sgn * h
+            o.set_c2(cp)
+            t, _, _ = o.run(d["nsteps"], d["dt"], d["src"], np.arange(d["shots"]), d["f0"],
+                            rec_nodes=d["rec"], n_shots=d["shots"])
+            Js.append(adjoint.misfit(t, d["obs"]))
+        fd.append((Js[0] - Js[1]) / (2 * h))
+    err = rel(g[els], fd)
+    say("fp32 gradient vs FD rel", err)
+    assert err <= 1e-4
+
+
+def test_unstable_dt_rejected(semlib, gpu_ok):
+    wl = workloads.workload("homog64", n=8)
+    s = semlib.Simulator(wl.vxy, wl.quads, wl.c2, wl.p, precision="f64")
+    inf = s.info()
+    assert 0 < inf["dt"] < inf["dt_stable"]
+    o = solver.SEM(wl.vxy, wl.quads, wl.c2, wl.p)
+    assert inf["lambda_max"] == pytest.approx(o.lambda_max(400), rel=2e-2)
+    with pytest.raises(semlib.SemError) as ei:
+        semlib.Simulator(wl.vxy, wl.quads, wl.c2, wl.p, precision="f64", dt=1.5 * inf["dt_stable"])
+    assert ei.value.status == "UNSTABLE_DT"
