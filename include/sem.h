@@ -75,8 +75,10 @@ typedef struct {
     double dt;               /* time step; 0 = cfl * min_e(dx_min,e / c_e)              */
     double cfl;              /* CFL number of the default dt; 0 = 0.3                  */
     void* stream;            /* hipStream_t for all device work; NULL = default stream */
-    int32_t tile_elems;      /* elements per workgroup tile; 0 = automatic              */
+    int32_t tile_elems;      /* > 0: fixed tiles of this many elements; 0 = adaptive     */
     int32_t shot_lanes;      /* shots per element inside a workgroup; 0 = automatic     */
+    int32_t tile_items;      /* adaptive tiles: own + halo elements per tile; 0 = auto  */
+    int32_t block_threads;   /* single-shot workgroup size 256/512/1024; 0 = automatic  */
 } sem_options;
 
 typedef struct {
@@ -87,9 +89,12 @@ typedef struct {
     int32_t precision;
     int32_t n_sources;       /* after merging sources on the same (node, shot)         */
     int32_t n_receivers;
-    int32_t tile_elems;
+    int32_t tile_elems;      /* fixed tile size, 0 when tiles are adaptive              */
     int32_t shot_lanes;
     int32_t max_owned_nodes; /* largest owned-node range of a tile                      */
+    int32_t tile_items;      /* adaptive cap on own + halo elements per tile            */
+    int32_t geometry_on_the_fly; /* 1: geometric factors computed in-kernel per step   */
+    int32_t block_threads;   /* threads per workgroup of the step kernel                */
     int64_t n_tiles;
     int64_t halo_elements;   /* sum over tiles of neighbour elements recomputed         */
     int64_t step;            /* steps taken since the last reset                        */

@@ -31,6 +31,7 @@ struct sem_ctx {
     sem::MeshIn mesh;                 // pointers valid only during sem_create
     int precision = SEM_F32;
     int S = 1, SL = 1;
+    int geo = 0;                      // 1: geometric factors computed in-kernel
     int device = -1;
     bool host_only = true;
     hipStream_t stream = nullptr;
@@ -119,16 +120,22 @@ sem::StepArgs<T> base_args(sem_ctx* c) {
     a.G_bytes = (uint32_t)c->G.bytes;
     a.c2_bytes = (uint32_t)c->c2.bytes;
     a.state_bytes = (uint32_t)((size_t)P.nn * c->S * c->wsize);
+    // bounds of the buffer-resource reads of dt/M use the same byte count as the state
     a.tile_eb = (const int32_t*)c->tile_eb.p;
     a.tile_nb = (const int32_t*)c->tile_nb.p;
     a.halo_b = (const int32_t*)c->halo_b.p;
     a.halo = (const int32_t*)c->halo.p;
     a.n_slices = c->S / c->SL;
+    a.lds_own = (P.max_owned + 63) & ~63;   // prefetch chunks are 64 entries
     a.dt = (T)P.dt;
     a.n_rec = c->n_rec;
     a.f0 = c->f0;
     a.t0 = c->t0;
     for (int i = 0; i < P.n * P.n; ++i) a.D[i] = (T)P.D[i];
+    for (int i = 0; i < P.n; ++i) {
+        a.xi[i] = (T)P.xi[i];
+        a.w[i] = (T)P.w[i];
+    }
     return a;
 }
 
@@ -137,7 +144,7 @@ size_t lds_bytes(const sem_ctx* c) { return (size_t)c->plan.max_owned * c->SL * 
 template <typename T>
 int launch(sem_ctx* c, const sem::StepArgs<T>& a) {
     const int64_t nt = (int64_t)c->plan.tile_eb.size() - 1;
-    SEM_HIP(c, sem::launch_step<T>(c->plan.p, c->SL, nt, lds_bytes(c), a, c->stream));
+    SEM_HIP(c, sem::launch_step<T>(c->plan.p, c->SL, c->geo, nt, lds_bytes(c), a, c->stream));
     return SEM_OK;
 }
 
@@ -221,6 +228,11 @@ int power_iteration(sem_ctx* c, int iters) {
         std::swap(c->u[0], c->u[1]);
     }
     dev_free(nrm);
+    if (!std::isfinite(lam) || lam < 0.0) {
+        c->lambda_max = lam;
+        c->dt_stable = 0.0;
+        return fail(c, SEM_ERR_UNSTABLE_DT, "stiffness apply produced a non-finite eigenvalue estimate");
+    }
     c->lambda_max = lam;
     c->dt_stable = lam > 0.0 ? 2.0 / std::sqrt(lam) : INFINITY;
     return zero_state<T>(c);
@@ -238,25 +250,46 @@ int set_device(sem_ctx* c) {
     return SEM_OK;
 }
 
+// Element arrays in the layout of the context's kernel: the single-shot row kernel reads
+// element-major records (node ids [E][nq]; [E][8] = bilinear coefficients, c^2, 0); the
+// shot-batch kernel reads 64-element blocks ([E/64][nq][64] ids, [E/64][3][nq][64] factors).
 template <typename T>
-int upload_mesh(sem_ctx* c) {
+int upload_geometry(sem_ctx* c) {
     const sem::Plan& P = c->plan;
-    // element-blocked device layouts [E/64][component][q][64] (padding repeats element 0)
-    const int64_t nq = P.nq, nblk = (P.ne + 63) / 64;
-    {
-        std::vector<int32_t> cb((size_t)nblk * nq * 64);
-        std::vector<double> gb((size_t)nblk * 3 * nq * 64);
-        for (int64_t e = 0; e < nblk * 64; ++e) {
-            const int64_t src = e < P.ne ? e : 0, b = e / 64, l = e % 64;
-            for (int64_t q = 0; q < nq; ++q) {
-                cb[(b * nq + q) * 64 + l] = P.conn_soa[q * P.ne + src];
-                for (int64_t k = 0; k < 3; ++k)
-                    gb[((b * 3 + k) * nq + q) * 64 + l] = P.G_soa[(k * nq + q) * P.ne + src];
-            }
+    const int64_t nq = P.nq, ne = P.ne;
+    if (c->geo) {
+        std::vector<int32_t> cb((size_t)ne * nq);
+        std::vector<double> gb((size_t)ne * 8, 0.0);
+        for (int64_t e = 0; e < ne; ++e) {
+            for (int64_t q = 0; q < nq; ++q) cb[e * nq + q] = P.conn_soa[q * ne + e];
+            for (int64_t k = 0; k < 6; ++k) gb[e * 8 + k] = P.bilin[k * ne + e];
+            gb[e * 8 + 6] = P.c2[e];
         }
         SEM_HIP(c, upload(c, c->conn, cb));
         SEM_HIP(c, upload_real(c, c->G, gb));
+        return SEM_OK;
     }
+    const int64_t nblk = (ne + 63) / 64;
+    std::vector<int32_t> cb((size_t)nblk * nq * 64);
+    std::vector<double> gb((size_t)nblk * 3 * nq * 64);
+    for (int64_t e = 0; e < nblk * 64; ++e) {
+        const int64_t src = e < ne ? e : 0, b = e / 64, l = e % 64;
+        for (int64_t q = 0; q < nq; ++q) {
+            cb[(b * nq + q) * 64 + l] = P.conn_soa[q * ne + src];
+            for (int64_t k = 0; k < 3; ++k)
+                gb[((b * 3 + k) * nq + q) * 64 + l] = P.G_soa[(k * nq + q) * ne + src];
+        }
+    }
+    SEM_HIP(c, upload(c, c->conn, cb));
+    SEM_HIP(c, upload_real(c, c->G, gb));
+    return SEM_OK;
+}
+
+template <typename T>
+int upload_mesh(sem_ctx* c) {
+    const sem::Plan& P = c->plan;
+    int rc = upload_geometry<T>(c);
+    if (rc) return rc;
     SEM_HIP(c, upload_real(c, c->c2, P.c2));
     SEM_HIP(c, upload_real(c, c->dtminv, P.minv, P.dt));
     SEM_HIP(c, upload(c, c->tile_eb, P.tile_eb));
@@ -280,13 +313,18 @@ int pick_shot_lanes(int S, int requested) {
     return sl;
 }
 
-int pick_tile(int p, int sl, int precision, int requested) {
+// Adaptive tiles: one workgroup pass covers kBlock / shot_lanes elements; single-shot
+// tiles fill exactly one pass, shot batches up to four. The LDS accumulator of the owned
+// nodes stays within 64 KB so several workgroups share a CU.
+int pick_tile_items(int p, int sl, int row_block, int requested) {
     if (requested > 0) return requested;
-    // keep the LDS accumulator of a workgroup near 32 KB: owned nodes ~ p^2 per element
+    // single shot: one pass of the row kernel; shot batches: four passes of 256 threads
+    return sl == 1 ? (64 / (p + 1)) * (row_block / 64) : 4 * sem::kBlock / sl;
+}
+
+int pick_max_owned(int sl, int precision) {
     const int word = precision == SEM_F64 ? 8 : 4;
-    int t = 32768 / (p * p * sl * word);
-    t = std::max(16, std::min(256, t));
-    return t;
+    return 65536 / (sl * word);
 }
 
 // owning tile of a new node id
@@ -578,7 +616,23 @@ int sem_create(const sem_mesh* mesh, const sem_options* opt, sem_ctx** out) {
     po.seed = opt->seed;
     po.dt = opt->dt;
     po.cfl = opt->cfl;
-    po.tile_elems = pick_tile(opt->p, c->SL, opt->precision, opt->tile_elems);
+    po.tile_elems = opt->tile_elems;
+    // measured on the layered 1024^2 p=4 mesh: FP32 256 threads x 1 pass, FP64 512 x 1 pass
+    const int row_block = opt->block_threads > 0 ? opt->block_threads : (opt->precision == SEM_F64 ? 512 : 256);
+    if (row_block != 256 && row_block != 512 && row_block != 1024) {
+        g_create_error = "block_threads must be 256, 512 or 1024";
+        delete c;
+        return SEM_ERR_INVALID_ARG;
+    }
+    // passes of the row kernel whose loads are batched: enough to cover one tile, <= 4
+    const int epb = (64 / (opt->p + 1)) * (row_block / 64);
+    const int max_np = row_block == 256 ? 4 : (row_block == 512 ? 2 : 1);
+    po.tile_items = pick_tile_items(opt->p, c->SL, row_block, opt->tile_items);
+    if (opt->tile_items <= 0 && c->SL == 1) po.tile_items = epb;
+    int np = 1;
+    while (np < max_np && np * epb < (opt->tile_elems > 0 ? opt->tile_elems : po.tile_items)) np *= 2;
+    po.max_owned = pick_max_owned(c->SL, opt->precision);
+    c->geo = c->S == 1 ? row_block * 8 + np : 0;     // single shot: row kernel, in-kernel geometry
     int code = SEM_OK;
     std::string err;
     try {
@@ -630,6 +684,9 @@ int sem_get_info(const sem_ctx* c, sem_info* info) {
     info->tile_elems = P.tile_elems;
     info->shot_lanes = c->SL;
     info->max_owned_nodes = P.max_owned;
+    info->tile_items = P.tile_items;
+    info->geometry_on_the_fly = c->geo ? 1 : 0;
+    info->block_threads = c->geo ? c->geo / 8 : sem::kBlock;
     info->n_tiles = P.tile_eb.empty() ? 0 : (int64_t)P.tile_eb.size() - 1;
     info->halo_elements = (int64_t)P.halo.size();
     info->step = c->step;
@@ -639,7 +696,12 @@ int sem_get_info(const sem_ctx* c, sem_info* info) {
     const double w = (double)c->wsize, nq = (double)P.nq;
     // algorithmic bytes: per element nq indices + 3 nq geometric factors + c2; per node
     // dt/M plus read u, v and write u, v for every shot
-    info->alg_bytes_per_step = (double)P.ne * (nq * 4.0 + 3.0 * nq * w + w) +
+    // algorithmic bytes: per element nq node indices, the geometry (6 bilinear-map
+    // coefficients when computed in-kernel, else 3 nq stored factors) and c2; per node
+    // dt/M plus read u, v and write u, v for every shot
+    // (row kernel: one 8-word record holding the 6 coefficients, c2 and padding)
+    const double elem_words = c->geo ? 8.0 : 3.0 * nq + 1.0;
+    info->alg_bytes_per_step = (double)P.ne * (nq * 4.0 + elem_words * w) +
                                (double)P.nn * (w + 4.0 * w * c->S);
     const double n = (double)P.n;
     info->alg_flops_per_step = (double)P.ne * c->S * (8.0 * n * n * n + 7.0 * n * n) +
@@ -695,6 +757,10 @@ int sem_set_c2(sem_ctx* c, const double* c2) {
     int rc = set_device(c);
     if (rc) return rc;
     SEM_HIP(c, upload_real(c, c->c2, c->plan.c2));
+    if (c->geo) {
+        rc = c->precision == SEM_F64 ? upload_geometry<double>(c) : upload_geometry<float>(c);
+        if (rc) return rc;
+    }
     rc = c->precision == SEM_F64 ? power_iteration<double>(c, 60) : power_iteration<float>(c, 60);
     if (rc) return rc;
     if (!(c->plan.dt < c->dt_stable))

@@ -7,15 +7,19 @@
 
 namespace sem {
 
-constexpr int kBlock = 256;     // threads per workgroup of every kernel
+constexpr int kBlock = 256;     // threads per workgroup of the shot-batch and utility kernels
+constexpr int kRowBlock = 1024; // largest workgroup of the single-shot row kernel
 constexpr int kMaxP = 7;
 
 // Arguments of the fused step kernel. All arrays use the new (curve) numbering.
 template <typename T>
 struct StepArgs {
     // mesh
-    const int32_t* conn;      // [E/64][nq][64] global node of local node q of element e
-    const T* G;               // [E/64][3][nq][64] geometric factors (11, 12, 22)
+    // shot-batch kernel: conn [E/64][nq][64], G [E/64][3][nq][64] geometric factors
+    // (11, 12, 22); row kernel: conn [E][nq], G [E][8] = six bilinear-map derivative
+    // coefficients, c^2, padding
+    const int32_t* conn;
+    const T* G;
     const T* c2;              // [E]
     const T* dtminv;          // [N] dt / lumped mass
     int64_t E;
@@ -28,6 +32,7 @@ struct StepArgs {
     const int32_t* halo_b;    // [T+1]
     const int32_t* halo;      // halo elements of all tiles
     int32_t n_slices;         // S / shot_lanes
+    int32_t lds_own;          // row kernel: owned-node LDS arrays hold this many entries
     // state: reads u_in, writes u_out, updates v in place
     const T* u_in;
     T* u_out;
@@ -54,12 +59,19 @@ struct StepArgs {
     // gradient pairing: grad[e] += sum_s (Khat_e u_in_e) . (u_pair_e)
     const T* u_pair;
     double* grad;
-    // 1D derivative matrix D[i*(p+1) + j] = l_j'(xi_i)
+    // 1D GLL nodes, weights and derivative matrix D[i*(p+1) + j] = l_j'(xi_i)
+    T xi[kMaxP + 1];
+    T w[kMaxP + 1];
     T D[(kMaxP + 1) * (kMaxP + 1)];
 };
 
+// geo = threads * 8 + passes (threads 256/512/1024, passes 1/2/4 batched per round of
+// loads): single-shot row kernel, geometric factors computed in-kernel (shot_lanes 1);
+// geo = 0: shot-batch kernel.
+// lds_bytes is the owned-node accumulator, the launcher adds the row kernel's stage.
+// Elements per workgroup pass of the row kernel: (64 / (p+1)) * (threads / 64).
 template <typename T>
-hipError_t launch_step(int p, int shot_lanes, int64_t n_tiles, size_t lds_bytes,
+hipError_t launch_step(int p, int shot_lanes, int geo, int64_t n_tiles, size_t lds_bytes,
                        const StepArgs<T>& a, hipStream_t stream);
 
 // out[s][old] = in[new][s]  (new -> old node map)

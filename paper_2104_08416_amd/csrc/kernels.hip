@@ -69,6 +69,59 @@ __device__ __forceinline__ int bload<int>(rsrc_t r, uint32_t off) {
     return (int)__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
 }
 
+// N consecutive dwords with the widest loads available (16, 8, then 4 bytes)
+template <int N>
+__device__ __forceinline__ void load_ids(rsrc_t r, uint32_t off, int (&out)[N]) {
+    int k = 0;
+#pragma unroll
+    for (; k + 4 <= N; k += 4) {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, off + 4u * k, 0, 0);
+        out[k] = (int)v[0]; out[k + 1] = (int)v[1]; out[k + 2] = (int)v[2]; out[k + 3] = (int)v[3];
+    }
+    if constexpr (N % 4 >= 2) {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, off + 4u * k, 0, 0);
+        out[k] = (int)v[0]; out[k + 1] = (int)v[1];
+        k += 2;
+    }
+    if constexpr (N % 2 == 1) out[N - 1] = (int)__builtin_amdgcn_raw_buffer_load_b32(r, off + 4u * (N - 1), 0, 0);
+}
+
+// one element record of 8 words (bilinear coefficients, c^2, padding) in 16-byte loads
+__device__ __forceinline__ void load_rec8(rsrc_t r, uint32_t off, float (&out)[8]) {
+    // lanes converted by value: __builtin_bit_cast applied to a vector-element lvalue
+    // reads lane 0 for every index
+    const auto v0 = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+    const auto v1 = __builtin_amdgcn_raw_buffer_load_b128(r, off + 16u, 0, 0);
+    out[0] = __uint_as_float(v0[0]);
+    out[1] = __uint_as_float(v0[1]);
+    out[2] = __uint_as_float(v0[2]);
+    out[3] = __uint_as_float(v0[3]);
+    out[4] = __uint_as_float(v1[0]);
+    out[5] = __uint_as_float(v1[1]);
+    out[6] = __uint_as_float(v1[2]);
+    out[7] = __uint_as_float(v1[3]);
+}
+__device__ __forceinline__ void load_rec8(rsrc_t r, uint32_t off, double (&out)[8]) {
+#pragma unroll
+    for (int k = 0; k < 8; k += 2) {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, off + 8u * k, 0, 0);
+        out[k] = __builtin_bit_cast(double, ((unsigned long long)v[1] << 32) | v[0]);
+        out[k + 1] = __builtin_bit_cast(double, ((unsigned long long)v[3] << 32) | v[2]);
+    }
+}
+
+// Copy `ndw` consecutive dwords starting at byte `off` of a buffer into LDS with
+// direct-to-LDS loads (no registers): each wave moves 64-dword chunks; the data lands
+// asynchronously and is visible to the workgroup after s_waitcnt vmcnt(0) + barrier.
+template <int RB>
+__device__ __forceinline__ void lds_prefetch(rsrc_t r, uint32_t off, void* lds, int ndw) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int c = wave; c * 64 < ndw; c += RB / 64) {
+        auto* dst = (__attribute__((address_space(3))) void*)((char*)lds + c * 256);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(r, dst, 4, off + (uint32_t)(c * 64 + lane) * 4u, 0, 0, 0);
+    }
+}
+
 // Scheduling fence: the machine scheduler may not move instructions across it, so loads
 // of one stage are not hoisted into the previous one (bounds the registers live at once).
 __device__ __forceinline__ void stage_fence() { __builtin_amdgcn_sched_barrier(0); }
@@ -80,7 +133,11 @@ __device__ __forceinline__ T group_sum(T v) {
     return v;
 }
 
-template <typename T, int P, int SL>
+// 1/x: hardware reciprocal in FP32 (1 ulp), correctly rounded division in FP64
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+
+template <typename T, int P, int SL, int GEO>
 __global__ void __launch_bounds__(kBlock, sizeof(T) == 8 ? SEM_MIN_WAVES_F64 : SEM_MIN_WAVES_F32) step_kernel(const StepArgs<T> a) {
     constexpr int N = P + 1, NQ = N * N;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -115,7 +172,7 @@ __global__ void __launch_bounds__(kBlock, sizeof(T) == 8 ? SEM_MIN_WAVES_F64 : S
         const int e = own ? eb + k : a.halo[hb + k - n_own_el];
         // element-blocked layouts: [E/64][component][q][64]; one byte offset per thread
         const uint32_t eoff = (uint32_t)((e >> 6) * (NQ * 64) + (e & 63)) * 4u;
-        const uint32_t goff = (uint32_t)((e >> 6) * (3 * NQ * 64) + (e & 63)) * (uint32_t)sizeof(T);
+        const uint32_t goff = (uint32_t)((e >> 6) * ((GEO ? 6 : 3 * NQ) * 64) + (e & 63)) * (uint32_t)sizeof(T);
         const uint32_t soff = (uint32_t)(s0 + s) * (uint32_t)sizeof(T);
         T u[NQ];
 #pragma unroll
@@ -129,6 +186,11 @@ __global__ void __launch_bounds__(kBlock, sizeof(T) == 8 ? SEM_MIN_WAVES_F64 : S
         //   r[a, j] += sum_i D[i, a] f1[i, j]   (first-axis flux of row j is complete)
         //   r[a, b] += D[j, b] f2[a, j]          (second-axis flux summed over rows)
         // so only u, r and one row of flux are live.
+        T bl[GEO ? 6 : 1];
+        if constexpr (GEO) {
+#pragma unroll
+            for (int c = 0; c < 6; ++c) bl[c] = bload<T>(r_G, goff + c * 64 * (uint32_t)sizeof(T));
+        }
         T r[NQ];
 #pragma unroll
         for (int q = 0; q < NQ; ++q) r[q] = T(0);
@@ -144,9 +206,23 @@ __global__ void __launch_bounds__(kBlock, sizeof(T) == 8 ? SEM_MIN_WAVES_F64 : S
                     gy += a.D[j * N + m] * u[i + N * m];
                 }
                 const int q = i + N * j;
-                const T g11 = bload<T>(r_G, goff + q * 64 * (uint32_t)sizeof(T));
-                const T g12 = bload<T>(r_G, goff + (NQ + q) * 64 * (uint32_t)sizeof(T));
-                const T g22 = bload<T>(r_G, goff + (2 * NQ + q) * 64 * (uint32_t)sizeof(T));
+                T g11, g12, g22;
+                if constexpr (GEO) {
+                    // Jacobian of the bilinear map at (xi_i, xi_j), then
+                    // G = w_i w_j detJ J^-1 J^-T
+                    const T xs = bl[0] + bl[2] * a.xi[j];
+                    const T xt = bl[1] + bl[2] * a.xi[i];
+                    const T ys = bl[3] + bl[5] * a.xi[j];
+                    const T yt = bl[4] + bl[5] * a.xi[i];
+                    const T sc = (a.w[i] * a.w[j]) * recip(xs * yt - xt * ys);
+                    g11 = sc * (xt * xt + yt * yt);
+                    g12 = -sc * (xs * xt + ys * yt);
+                    g22 = sc * (xs * xs + ys * ys);
+                } else {
+                    g11 = bload<T>(r_G, goff + q * 64 * (uint32_t)sizeof(T));
+                    g12 = bload<T>(r_G, goff + (NQ + q) * 64 * (uint32_t)sizeof(T));
+                    g22 = bload<T>(r_G, goff + (2 * NQ + q) * 64 * (uint32_t)sizeof(T));
+                }
                 f1[i] = g11 * gx + g12 * gy;
                 f2[i] = g12 * gx + g22 * gy;
             }
@@ -241,9 +317,232 @@ __global__ void __launch_bounds__(kBlock, sizeof(T) == 8 ? SEM_MIN_WAVES_F64 : S
     }
 }
 
-template <typename T, int P, int SL>
+// ---------------------------------------------------------------------------------------
+// Single-shot step, one thread per element row. p+1 consecutive lanes of a wave hold the
+// p+1 rows (second reference index j) of one element; a wave holds 64/(p+1) elements and
+// a 1024-thread workgroup 16 times that. The two contractions that run across rows (the
+// derivative along the second axis and its D^T) exchange one element's values through a
+// per-element LDS stage written and read by the same wave (LDS executes one wave's
+// instructions in order, so no barrier is needed). Geometric factors come from the six
+// bilinear-map coefficients of the element.
+// Waves per SIMD the row kernel's registers must allow; batching more passes per round of
+// loads keeps more values live, so it trades occupancy for fewer memory round trips.
+template <typename T, int P, int NP>
+constexpr int rows_waves() {
+    return sizeof(T) == 4 ? (NP == 1 ? (P <= 5 ? 8 : 6) : (NP == 2 ? 5 : 3)) : (NP == 1 ? 4 : (NP == 2 ? 3 : 2));
+}
+
+template <typename T, int P, int RB, int NP>
+__global__ void __attribute__((amdgpu_flat_work_group_size(RB, RB),
+                               amdgpu_waves_per_eu(rows_waves<T, P, NP>(), 8)))
+step_rows_kernel(const StepArgs<T> a) {
+    constexpr int kRowBlock = RB;                      // threads of this workgroup
+    constexpr int N = P + 1, NQ = N * N;
+    constexpr int NQP = (NQ + 3) & ~3;                 // 16-byte aligned stage stride
+    constexpr int EPW = 64 / N;                        // elements per wave
+    constexpr int EPB = EPW * (kRowBlock / 64);        // elements per workgroup pass
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* stage = reinterpret_cast<T*>(smem_raw);          // [EPB][NQP]
+    T* acc = stage + EPB * NQP;                         // [owned nodes]
+    // owned v, u_in and dt/M prefetched for the update phase: [3][a.lds_own] (64-aligned)
+    T* pre_v = acc + a.lds_own;
+    T* pre_u = pre_v + a.lds_own;
+    T* pre_m = pre_u + a.lds_own;
+
+    const int logical = xcd_logical_block();
+    const int tile = logical;
+    const int nb = a.tile_nb[tile];
+    const int nown = a.tile_nb[tile + 1] - nb;
+    const int eb = a.tile_eb[tile];
+    const int n_own_el = a.tile_eb[tile + 1] - eb;
+    const int hb = a.halo_b[tile];
+    const int n_items = n_own_el + (a.halo_b[tile + 1] - hb);
+
+    const rsrc_t r_conn = make_rsrc(a.conn, a.conn_bytes);
+    const rsrc_t r_G = make_rsrc(a.G, a.G_bytes);
+    const rsrc_t r_u = make_rsrc(a.u_in, a.state_bytes);
+    const rsrc_t r_pair = make_rsrc(a.u_pair, a.u_pair ? a.state_bytes : 0u);
+
+    if (a.mode == 0) {
+        // the update phase's operands travel while the elements are processed
+        const int ndw = nown * (int)(sizeof(T) / 4);
+        const uint32_t off = (uint32_t)nb * (uint32_t)sizeof(T);
+        lds_prefetch<RB>(make_rsrc(a.v, a.state_bytes), off, pre_v, ndw);
+        lds_prefetch<RB>(r_u, off, pre_u, ndw);
+        lds_prefetch<RB>(make_rsrc(a.dtminv, a.state_bytes), off, pre_m, ndw);
+    }
+    for (int i = threadIdx.x; i < nown; i += kRowBlock) acc[i] = T(0);
+    __syncthreads();
+
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int kw = lane / N;                           // element slot inside the wave
+    const int j = lane - kw * N;                       // row of that element
+    const int slot = wave * EPW + kw;
+    T* st = stage + slot * NQP;
+    // The row j of a thread never changes: keep row j and column j of D, xi_j and w_j in
+    // registers (selected from the uniform kernel arguments, no per-lane memory reads).
+    T Dj[N], DjT[N], xij = a.xi[0], wj = a.w[0];
+#pragma unroll
+    for (int m = 0; m < N; ++m) {
+        Dj[m] = a.D[m];
+        DjT[m] = a.D[m * N];
+    }
+#pragma unroll
+    for (int jj = 1; jj < N; ++jj) {
+        if (j == jj) {
+#pragma unroll
+            for (int m = 0; m < N; ++m) {
+                Dj[m] = a.D[jj * N + m];
+                DjT[m] = a.D[m * N + jj];
+            }
+            xij = a.xi[jj];
+            wj = a.w[jj];
+        }
+    }
+    // NP passes at a time: every pass's indices and geometry are requested first, then
+    // every pass's gathers, so a tile costs two memory round trips instead of 2 NP.
+    for (int base = 0; base < n_items; base += NP * EPB) {
+        int es[NP], idx[NP][N];
+        bool act[NP];
+        T bl[NP][8], u[NP][N];
+#pragma unroll
+        for (int pp = 0; pp < NP; ++pp) {
+            const int k = base + pp * EPB + slot;
+            act[pp] = kw < EPW && k < n_items;
+            es[pp] = 0;
+            if (act[pp]) {
+                const int e = k < n_own_el ? eb + k : a.halo[hb + k - n_own_el];
+                es[pp] = e;
+                // element-major records: row j's node ids, then the element's geometry + c^2
+                load_ids<N>(r_conn, (uint32_t)(e * NQ + N * j) * 4u, idx[pp]);
+                load_rec8(r_G, (uint32_t)e * 8u * (uint32_t)sizeof(T), bl[pp]);
+            }
+        }
+#pragma unroll
+        for (int pp = 0; pp < NP; ++pp) {
+            if (act[pp]) {
+#pragma unroll
+                for (int i = 0; i < N; ++i) u[pp][i] = bload<T>(r_u, (uint32_t)idx[pp][i] * (uint32_t)sizeof(T));
+            }
+        }
+#pragma unroll
+        for (int pp = 0; pp < NP; ++pp) {
+            if (!act[pp]) continue;
+            const int k = base + pp * EPB + slot;
+            const bool own = k < n_own_el;
+            const int e = es[pp];
+#pragma unroll
+            for (int i = 0; i < N; ++i) st[i + N * j] = u[pp][i];
+            // reference gradient at the row's points: d/dxi from the row, d/deta from the stage
+            T gx[N], gy[N];
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                T sacc = T(0);
+#pragma unroll
+                for (int m = 0; m < N; ++m) sacc += a.D[i * N + m] * u[pp][m];
+                gx[i] = sacc;
+                gy[i] = T(0);
+            }
+#pragma unroll
+            for (int m = 0; m < N; ++m) {
+                const T djm = Dj[m];
+#pragma unroll
+                for (int i = 0; i < N; ++i) gy[i] += djm * st[i + N * m];
+            }
+            // geometric flux at (xi_i, xi_j); first-axis D^T stays in the row
+            const T xs = bl[pp][0] + bl[pp][2] * xij;
+            const T ys = bl[pp][3] + bl[pp][5] * xij;
+            T f2[N], r[N];
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                const T xt = bl[pp][1] + bl[pp][2] * a.xi[i];
+                const T yt = bl[pp][4] + bl[pp][5] * a.xi[i];
+                const T sc = (a.w[i] * wj) * recip(xs * yt - xt * ys);
+                const T g11 = sc * (xt * xt + yt * yt);
+                const T g12 = -sc * (xs * xt + ys * yt);
+                const T g22 = sc * (xs * xs + ys * ys);
+                const T f1 = g11 * gx[i] + g12 * gy[i];
+                f2[i] = g12 * gx[i] + g22 * gy[i];
+                gx[i] = f1;
+            }
+#pragma unroll
+            for (int aa = 0; aa < N; ++aa) {
+                T sacc = T(0);
+#pragma unroll
+                for (int i = 0; i < N; ++i) sacc += a.D[i * N + aa] * gx[i];
+                r[aa] = sacc;
+            }
+            // second-axis D^T across rows: r[a, j] += sum_m D[m, j] f2[a, m]
+#pragma unroll
+            for (int i = 0; i < N; ++i) st[i + N * j] = f2[i];
+#pragma unroll
+            for (int m = 0; m < N; ++m) {
+                const T dmj = DjT[m];
+#pragma unroll
+                for (int aa = 0; aa < N; ++aa) r[aa] += dmj * st[aa + N * m];
+            }
+            if (a.grad != nullptr && own) {
+                T dot = T(0);
+#pragma unroll
+                for (int aa = 0; aa < N; ++aa)
+                    dot += r[aa] * bload<T>(r_pair, (uint32_t)idx[pp][aa] * (uint32_t)sizeof(T));
+                atomicAdd(&a.grad[e], (double)dot);
+            }
+#pragma unroll
+            for (int aa = 0; aa < N; ++aa) {
+                const int loc = idx[pp][aa] - nb;
+                if ((unsigned)loc < (unsigned)nown) atomicAdd(&acc[loc], bl[pp][6] * r[aa]);
+            }
+        }
+    }
+    __builtin_amdgcn_s_waitcnt(0);                     // this wave's LDS prefetches landed
+    __syncthreads();
+
+    if (a.src_b != nullptr) {
+        const int sb = a.src_b[tile], se = a.src_b[tile + 1];
+        if (se > sb) {
+            const T amp = (T)ricker(a.src_t, a.f0, a.t0);
+            for (int i = sb + threadIdx.x; i < se; i += kRowBlock)
+                if (a.src_shot[i] == 0) atomicAdd(&acc[a.src_loc[i]], -a.src_w[i] * amp);
+            __syncthreads();
+        }
+    }
+    if (a.inj != nullptr) {
+        const int rb = a.rec_b[tile], re = a.rec_b[tile + 1];
+        if (re > rb) {
+            for (int i = rb + threadIdx.x; i < re; i += kRowBlock) {
+                const T val = a.inj[(int64_t)a.rec_idx[i] * a.inj_cols + a.inj_col];
+                atomicAdd(&acc[a.rec_loc[i]], -val * a.inj_scale);
+            }
+            __syncthreads();
+        }
+    }
+    if (a.mode == 0) {
+        // owned-node update from the prefetched operands
+        for (int i = threadIdx.x; i < nown; i += kRowBlock) {
+            const T vn = pre_v[i] - pre_m[i] * acc[i];
+            const T un = pre_u[i] + a.dt * vn;
+            a.v[nb + i] = vn;
+            a.u_out[nb + i] = un;
+            acc[i] = un;
+        }
+        if (a.trace != nullptr) {
+            const int rb = a.rec_b[tile], re = a.rec_b[tile + 1];
+            if (re > rb) {
+                __syncthreads();
+                for (int i = rb + threadIdx.x; i < re; i += kRowBlock)
+                    a.trace[(int64_t)a.rec_idx[i] * a.trace_cols + a.trace_col] = acc[a.rec_loc[i]];
+            }
+        }
+    } else {
+        for (int i = threadIdx.x; i < nown; i += kRowBlock)
+            a.r_out[nb + i] = a.mode == 2 ? a.dtminv[nb + i] * acc[i] : acc[i];
+    }
+}
+
+template <typename T, int P, int SL, int GEO>
 hipError_t launch_one(int64_t n_tiles, size_t lds, const StepArgs<T>& a, hipStream_t st) {
-    auto fn = step_kernel<T, P, SL>;
+    auto fn = step_kernel<T, P, SL, GEO>;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -254,16 +553,44 @@ hipError_t launch_one(int64_t n_tiles, size_t lds, const StepArgs<T>& a, hipStre
     return hipGetLastError();
 }
 
+template <typename T, int P, int RB, int NP>
+hipError_t launch_rows(int64_t n_tiles, size_t lds, const StepArgs<T>& a, hipStream_t st) {
+    auto fn = step_rows_kernel<T, P, RB, NP>;
+    constexpr int N = P + 1, NQP = (N * N + 3) & ~3, EPB = (64 / N) * (RB / 64);
+    // stage + accumulator + three prefetch arrays of a.lds_own entries each
+    lds = (size_t)EPB * NQP * sizeof(T) + (size_t)4 * a.lds_own * sizeof(T);
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(fn, dim3((unsigned)n_tiles), dim3(RB), lds, st, a);
+    return hipGetLastError();
+}
+
 template <typename T, int P>
-hipError_t launch_p(int sl, int64_t nt, size_t lds, const StepArgs<T>& a, hipStream_t st) {
+hipError_t launch_p(int sl, int geo, int64_t nt, size_t lds, const StepArgs<T>& a, hipStream_t st) {
+    if (geo) {
+        if (sl != 1) return hipErrorInvalidValue;
+        // geo = threads per workgroup * 8 + passes batched per round of loads
+        switch (geo) {
+            case 256 * 8 + 1: return launch_rows<T, P, 256, 1>(nt, lds, a, st);
+            case 256 * 8 + 2: return launch_rows<T, P, 256, 2>(nt, lds, a, st);
+            case 256 * 8 + 4: return launch_rows<T, P, 256, 4>(nt, lds, a, st);
+            case 512 * 8 + 1: return launch_rows<T, P, 512, 1>(nt, lds, a, st);
+            case 512 * 8 + 2: return launch_rows<T, P, 512, 2>(nt, lds, a, st);
+            case 1024 * 8 + 1: return launch_rows<T, P, 1024, 1>(nt, lds, a, st);
+            default: return hipErrorInvalidValue;
+        }
+    }
     switch (sl) {
-        case 1: return launch_one<T, P, 1>(nt, lds, a, st);
-        case 2: return launch_one<T, P, 2>(nt, lds, a, st);
-        case 4: return launch_one<T, P, 4>(nt, lds, a, st);
-        case 8: return launch_one<T, P, 8>(nt, lds, a, st);
-        case 16: return launch_one<T, P, 16>(nt, lds, a, st);
-        case 32: return launch_one<T, P, 32>(nt, lds, a, st);
-        case 64: return launch_one<T, P, 64>(nt, lds, a, st);
+        case 1: return launch_one<T, P, 1, 0>(nt, lds, a, st);
+        case 2: return launch_one<T, P, 2, 0>(nt, lds, a, st);
+        case 4: return launch_one<T, P, 4, 0>(nt, lds, a, st);
+        case 8: return launch_one<T, P, 8, 0>(nt, lds, a, st);
+        case 16: return launch_one<T, P, 16, 0>(nt, lds, a, st);
+        case 32: return launch_one<T, P, 32, 0>(nt, lds, a, st);
+        case 64: return launch_one<T, P, 64, 0>(nt, lds, a, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -339,15 +666,15 @@ inline unsigned grid_stride(int64_t n) {
 }  // namespace
 
 template <typename T>
-hipError_t launch_step(int p, int sl, int64_t nt, size_t lds, const StepArgs<T>& a, hipStream_t st) {
+hipError_t launch_step(int p, int sl, int geo, int64_t nt, size_t lds, const StepArgs<T>& a, hipStream_t st) {
     switch (p) {
-        case 1: return launch_p<T, 1>(sl, nt, lds, a, st);
-        case 2: return launch_p<T, 2>(sl, nt, lds, a, st);
-        case 3: return launch_p<T, 3>(sl, nt, lds, a, st);
-        case 4: return launch_p<T, 4>(sl, nt, lds, a, st);
-        case 5: return launch_p<T, 5>(sl, nt, lds, a, st);
-        case 6: return launch_p<T, 6>(sl, nt, lds, a, st);
-        case 7: return launch_p<T, 7>(sl, nt, lds, a, st);
+        case 1: return launch_p<T, 1>(sl, geo, nt, lds, a, st);
+        case 2: return launch_p<T, 2>(sl, geo, nt, lds, a, st);
+        case 3: return launch_p<T, 3>(sl, geo, nt, lds, a, st);
+        case 4: return launch_p<T, 4>(sl, geo, nt, lds, a, st);
+        case 5: return launch_p<T, 5>(sl, geo, nt, lds, a, st);
+        case 6: return launch_p<T, 6>(sl, geo, nt, lds, a, st);
+        case 7: return launch_p<T, 7>(sl, geo, nt, lds, a, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -391,7 +718,7 @@ hipError_t launch_grad_to_original(const double* acc, double* out, const int32_t
 }
 
 #define SEM_INSTANTIATE(T)                                                                        \
-    template hipError_t launch_step<T>(int, int, int64_t, size_t, const StepArgs<T>&, hipStream_t); \
+    template hipError_t launch_step<T>(int, int, int, int64_t, size_t, const StepArgs<T>&, hipStream_t); \
     template hipError_t launch_nodes_to_original<T>(const T*, T*, const int32_t*, int64_t, int32_t,   \
                                                     hipStream_t);                                 \
     template hipError_t launch_nodes_from_original<T>(const T*, T*, const int32_t*, int64_t,        \

@@ -289,58 +289,76 @@ int32_t nearest_node(const Plan& plan, double px, double py) {
     return best;
 }
 
-void build_tiles(Plan& P, int tile_elems) {
+void build_tiles(Plan& P, int tile_elems, int tile_items, int max_owned) {
     const int64_t ne = P.ne, nq = P.nq;
-    P.tile_elems = tile_elems;
-    const int64_t nt = (ne + tile_elems - 1) / tile_elems;
-    P.tile_eb.assign(nt + 1, 0);
-    P.tile_nb.assign(nt + 1, 0);
-    for (int64_t t = 0; t <= nt; ++t) P.tile_eb[t] = (int32_t)std::min<int64_t>(ne, t * tile_elems);
-    // owned range of tile t = nodes first touched by its elements. With first-touch
-    // numbering these are contiguous; the range start is the smallest id first touched.
-    std::vector<int32_t> first_tile(P.nn, INT32_MAX);
-    for (int64_t t = 0; t < nt; ++t)
-        for (int64_t e = P.tile_eb[t]; e < P.tile_eb[t + 1]; ++e)
-            for (int64_t q = 0; q < nq; ++q) {
-                const int32_t v = P.conn_soa[q * ne + e];
-                if (first_tile[v] == INT32_MAX) first_tile[v] = (int32_t)t;
-            }
-    // owned ranges must be contiguous and increasing
-    int64_t cur = 0;
-    for (int64_t t = 0; t < nt; ++t) {
-        P.tile_nb[t] = (int32_t)cur;
-        while (cur < P.nn && first_tile[cur] == t) ++cur;
-    }
-    P.tile_nb[nt] = (int32_t)cur;
-    P.max_owned = 0;
-    for (int64_t t = 0; t < nt; ++t)
-        P.max_owned = std::max<int32_t>(P.max_owned, P.tile_nb[t + 1] - P.tile_nb[t]);
-    // halo of tile t: elements of other tiles that touch a node owned by t
-    std::vector<int32_t> n2e_b(P.nn + 1, 0), n2e;
+    // node -> incident elements (new numbering)
+    std::vector<int32_t> n2e_b(P.nn + 1, 0), n2e((size_t)ne * nq);
     for (int64_t i = 0; i < ne * nq; ++i) n2e_b[P.conn_soa[i] + 1]++;
     for (int64_t i = 0; i < P.nn; ++i) n2e_b[i + 1] += n2e_b[i];
-    n2e.resize(ne * nq);
     {
         std::vector<int32_t> fill(n2e_b.begin(), n2e_b.end() - 1);
         for (int64_t q = 0; q < nq; ++q)
             for (int64_t e = 0; e < ne; ++e) n2e[fill[P.conn_soa[q * ne + e]]++] = (int32_t)e;
     }
-    P.halo_b.assign(nt + 1, 0);
+    auto node_of = [&](int64_t e, int64_t q) { return P.conn_soa[q * ne + e]; };
+    P.tile_elems = tile_elems > 0 ? tile_elems : 0;
+    P.tile_items = tile_elems > 0 ? 0 : tile_items;
+    P.tile_eb.assign(1, 0);
+    P.tile_nb.assign(1, 0);
+    P.halo_b.assign(1, 0);
     P.halo.clear();
-    std::vector<int32_t> buf;
-    for (int64_t t = 0; t < nt; ++t) {
-        buf.clear();
-        const int32_t eb = P.tile_eb[t], ee = P.tile_eb[t + 1];
-        for (int32_t v = P.tile_nb[t]; v < P.tile_nb[t + 1]; ++v)
-            for (int32_t k = n2e_b[v]; k < n2e_b[v + 1]; ++k) {
-                const int32_t e = n2e[k];
-                if (e < eb || e >= ee) buf.push_back(e);
+    // With first-touch numbering the nodes first touched by element e are exactly its ids
+    // >= node_hi (1 + largest id touched so far), so a tile's owned range is contiguous.
+    // Halo elements of a tile touch one of its owned nodes and lie later in the order.
+    std::vector<int32_t> mark(ne, -1), cand, fresh_halo;
+    int64_t e = 0;
+    int32_t node_hi = 0;
+    int32_t t = 0;
+    while (e < ne) {
+        const int64_t e0 = e;
+        const int32_t nb = node_hi;
+        int64_t halo_count = 0;
+        cand.clear();
+        while (e < ne) {
+            int32_t new_hi = node_hi;
+            for (int64_t q = 0; q < nq; ++q) new_hi = std::max(new_hi, node_of(e, q) + 1);
+            fresh_halo.clear();
+            for (int64_t q = 0; q < nq; ++q) {
+                const int32_t v = node_of(e, q);
+                if (v < node_hi) continue;
+                for (int32_t k = n2e_b[v]; k < n2e_b[v + 1]; ++k) {
+                    const int32_t f = n2e[k];
+                    if (f != e && mark[f] != t) { mark[f] = t; fresh_halo.push_back(f); }
+                }
             }
-        std::sort(buf.begin(), buf.end());
-        buf.erase(std::unique(buf.begin(), buf.end()), buf.end());
-        P.halo.insert(P.halo.end(), buf.begin(), buf.end());
-        P.halo_b[t + 1] = (int32_t)P.halo.size();
+            const bool was_halo = mark[e] == t && std::find(fresh_halo.begin(), fresh_halo.end(), (int32_t)e) == fresh_halo.end();
+            const int64_t own_after = e - e0 + 1;
+            const int64_t halo_after = halo_count - (was_halo ? 1 : 0) + (int64_t)fresh_halo.size();
+            bool stop;
+            if (tile_elems > 0) stop = own_after > tile_elems;
+            else stop = e > e0 && (own_after + halo_after > tile_items || new_hi - nb > max_owned);
+            if (stop) {
+                for (int32_t f : fresh_halo) mark[f] = -1;     // undo the tentative marks
+                break;
+            }
+            for (int32_t f : fresh_halo) cand.push_back(f);
+            if (was_halo) mark[e] = -1;                        // it is an own element now
+            halo_count = halo_after;
+            node_hi = new_hi;
+            ++e;
+        }
+        std::sort(cand.begin(), cand.end());
+        cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+        for (int32_t f : cand)
+            if (f >= e && mark[f] == t) P.halo.push_back(f);
+        P.tile_eb.push_back((int32_t)e);
+        P.tile_nb.push_back(node_hi);
+        P.halo_b.push_back((int32_t)P.halo.size());
+        ++t;
     }
+    P.max_owned = 0;
+    for (size_t k = 0; k + 1 < P.tile_nb.size(); ++k)
+        P.max_owned = std::max<int32_t>(P.max_owned, P.tile_nb[k + 1] - P.tile_nb[k]);
 }
 
 void element_geometry(const Plan& P, const MeshIn& m, int64_t e, double* g11, double* g12,
@@ -367,7 +385,7 @@ std::string build_plan(const MeshIn& m, const PlanOptions& opt, Plan& P, int& co
     if (m.ne < 1 || m.nv < 4 || !m.vxy || !m.quad || !m.c2) return "empty or null mesh";
     if (opt.elem_order < 0 || opt.elem_order > 3) return "unknown element order";
     if (opt.node_order < 0 || opt.node_order > 1) return "unknown node order";
-    if (opt.tile_elems < 1) return "tile_elems must be positive";
+    if (opt.tile_elems < 0 || (opt.tile_elems == 0 && opt.tile_items < 1)) return "bad tile size";
     for (int64_t e = 0; e < m.ne; ++e)
         if (!(m.c2[e] > 0.0) || !std::isfinite(m.c2[e])) return "c2 must be positive and finite";
     for (int64_t i = 0; i < 2 * m.nv; ++i)
@@ -526,9 +544,17 @@ std::string build_plan(const MeshIn& m, const PlanOptions& opt, Plan& P, int& co
     P.conn_soa.resize((size_t)nq * ne);
     P.G_soa.resize((size_t)3 * nq * ne);
     P.c2.resize(ne);
+    P.bilin.resize((size_t)6 * ne);
     for (int64_t k = 0; k < ne; ++k) {
         const int64_t e = P.elem_new2old[k];
         P.c2[k] = m.c2[e];
+        const Corners cc = corners(m, e);
+        P.bilin[0 * ne + k] = ((cc.x[1] - cc.x[0]) + (cc.x[2] - cc.x[3])) * 0.25;
+        P.bilin[1 * ne + k] = ((cc.x[3] - cc.x[0]) + (cc.x[2] - cc.x[1])) * 0.25;
+        P.bilin[2 * ne + k] = ((cc.x[0] - cc.x[1]) + (cc.x[2] - cc.x[3])) * 0.25;
+        P.bilin[3 * ne + k] = ((cc.y[1] - cc.y[0]) + (cc.y[2] - cc.y[3])) * 0.25;
+        P.bilin[4 * ne + k] = ((cc.y[3] - cc.y[0]) + (cc.y[2] - cc.y[1])) * 0.25;
+        P.bilin[5 * ne + k] = ((cc.y[0] - cc.y[1]) + (cc.y[2] - cc.y[3])) * 0.25;
         for (int q = 0; q < nq; ++q) {
             P.conn_soa[(size_t)q * ne + k] = P.node_old2new[P.conn0[e * nq + q]];
             for (int c = 0; c < 3; ++c)
@@ -537,7 +563,7 @@ std::string build_plan(const MeshIn& m, const PlanOptions& opt, Plan& P, int& co
     }
     P.minv.resize(nn);
     for (int64_t i = 0; i < nn; ++i) P.minv[i] = 1.0 / mass[P.node_new2old[i]];
-    if (opt.node_order == SEM_NODES_FIRST_TOUCH) build_tiles(P, opt.tile_elems);
+    if (opt.node_order == SEM_NODES_FIRST_TOUCH) build_tiles(P, opt.tile_elems, opt.tile_items, opt.max_owned);
     code = SEM_OK;
     return "";
 }

@@ -26,7 +26,9 @@ struct PlanOptions {
     uint64_t seed = 3;
     double dt = 0.0;
     double cfl = 0.3;
-    int tile_elems = 128;
+    int tile_elems = 0;      // > 0: fixed tiles of this many elements
+    int tile_items = 256;    // adaptive tiles: own + halo elements per tile at most this
+    int max_owned = 1 << 30; // adaptive tiles: owned nodes per tile at most this
 };
 
 struct Plan {
@@ -44,11 +46,14 @@ struct Plan {
     // device-bound arrays, new numbering
     std::vector<int32_t> conn_soa;           // [nq][ne] new node ids
     std::vector<double> G_soa;               // [3][nq][ne] w_a w_b detJ J^-1 J^-T (11, 12, 22)
+    std::vector<double> bilin;               // [6][ne] x_xi = c0 + c2 eta, x_eta = c1 + c2 xi,
+                                             //         y_xi = c3 + c5 eta, y_eta = c4 + c5 xi
     std::vector<double> c2;                  // [ne]
     std::vector<double> minv;                // [nn] 1 / lumped mass
     // tiling (new numbering): tile t has elements [tile_eb[t], tile_eb[t+1]), owns nodes
     // [tile_nb[t], tile_nb[t+1]), and recomputes halo[halo_b[t] .. halo_b[t+1]).
-    int tile_elems = 0;
+    int tile_elems = 0;                      // fixed tile size, 0 when adaptive
+    int tile_items = 0;                      // adaptive cap on own + halo elements
     std::vector<int32_t> tile_eb, tile_nb, halo_b, halo;
     int32_t max_owned = 0;
     double reorder_seconds = 0.0;
@@ -57,8 +62,10 @@ struct Plan {
 // Fills `plan` or returns a non-empty error string; `code` receives the sem_status.
 std::string build_plan(const MeshIn& mesh, const PlanOptions& opt, Plan& plan, int& code);
 
-// Rebuild the tiling of an existing plan for another tile size.
-void build_tiles(Plan& plan, int tile_elems);
+// (Re)build the tiling: fixed tiles of `tile_elems` elements when > 0, else adaptive tiles
+// that grow along the element order while own + halo elements <= tile_items and owned
+// nodes <= max_owned.
+void build_tiles(Plan& plan, int tile_elems, int tile_items, int max_owned);
 
 // Cell index along the generalized Hilbert curve over a W x H grid.
 int64_t hilbert_index(int64_t W, int64_t H, int64_t cx, int64_t cy);

@@ -103,6 +103,19 @@ def test_apply_stiffness_fp64(semlib, gpu_ok):
     assert rel(r, r_o) <= 1e-13
 
 
+def test_apply_stiffness_fp32(semlib, gpu_ok):
+    """FP32 stiffness apply against the FP64 oracle: rounding-level agreement."""
+    import torch
+    say("case apply fp32")
+    wl = workloads.workload("layered1024", n=48)
+    o = solver.SEM(wl.vxy, wl.quads, wl.c2, wl.p)
+    s = semlib.Simulator(wl.vxy, wl.quads, wl.c2, wl.p, precision="f32")
+    x = workloads.random_field(o.n_nodes, 1, seed=5)
+    r = s.apply_stiffness(torch.tensor(x, dtype=torch.float32, device="cuda")).cpu().numpy()
+    r_o = (o.K @ x.T).T
+    assert rel(r, r_o) <= 2e-6
+
+
 def test_resume_from_saved_fields(semlib, gpu_ok):
     """run(200) == run(100) + save (u, v) + restore into a fresh context + run(100)."""
     import torch
