@@ -153,3 +153,36 @@ class SEM:
 def standing_mode(node_xy, L: float, m: int, n: int):
     """phi = cos(m pi x / L) cos(n pi y / L), a Neumann eigenmode of the square."""
     return np.cos(m * np.pi * node_xy[:, 0] / L) * np.cos(n * np.pi * node_xy[:, 1] / L)
+
+
+def node_incidence(conn, n_nodes):
+    """CSR of the elements around every node: (start [N+1], elements [E*nq], local slot)."""
+    E, nq = conn.shape
+    flat = conn.ravel()
+    order = np.argsort(flat, kind="stable")
+    counts = np.bincount(flat, minlength=n_nodes)
+    start = np.concatenate([[0], np.cumsum(counts)])
+    return start, order // nq, order % nq
+
+
+def sampled_rows(vxy, quads, c2, p, conn, nodes, u):
+    """(K u)[nodes] and the lumped mass M[nodes], one node at a time, from the element
+    matrices of the elements around each node (Eqs. R and A-bar restricted to the rows of
+    the sampled nodes). ``u`` is [n_nodes] or [n_nodes, S]; returns (r [k(,S)], M [k])."""
+    start, elem, slot = node_incidence(conn, int(conn.max()) + 1)
+    nodes = np.asarray(nodes, dtype=np.int64)
+    ks = [np.arange(start[v], start[v + 1]) for v in nodes]
+    els = np.unique(np.concatenate([elem[k] for k in ks]))
+    Ke = _mesh.element_stiffness(vxy, quads, p, c2, elements=els)
+    det = _mesh.jacobians(vxy, quads[els], p)[4]
+    wq = _mesh.quadrature_weights(p)
+    pos = {int(e): i for i, e in enumerate(els)}
+    u = np.asarray(u, dtype=np.float64)
+    r = np.zeros((nodes.size,) + u.shape[1:])
+    M = np.zeros(nodes.size)
+    for i, k in enumerate(ks):
+        for e, q in zip(elem[k], slot[k]):
+            j = pos[int(e)]
+            r[i] += Ke[j, q] @ u[conn[e]]
+            M[i] += wq[q] * det[j, q]
+    return r, M
