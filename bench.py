@@ -117,7 +117,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--legs", default=",".join(ALL_LEGS))
     ap.add_argument("--quick", action="store_true", help="headline leg only")
-    ap.add_argument("--n", type=int, default=1024, help="elements per side of the headline mesh")
+    ap.add_argument("--n", type=int, default=None, help="elements per side of the headline mesh")
+    ap.add_argument("--order", default="hilbert", choices=["hilbert", "morton", "lex", "random"],
+                    help="element order of the headline leg")
+    ap.add_argument("--precision", default="f32", choices=["f32", "f64"], help="headline precision")
+    ap.add_argument("--workload", default="layered1024", choices=["layered1024", "graded1414", "batch512"],
+                    help="headline workload (default: the layered 1024^2 p=4 mesh)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -150,12 +155,13 @@ def main():
         out["copy_calib"] = {"bytes_per_launch": 2 * 4 * (1 << 28), "GBs": 2 * 4 * (1 << 28) / sec / 1e9}
         del src, dst
     # ---------------------------------------------------------------- headline
-    wl = workloads.workload("layered1024", n=args.n)
-    log(f"[bench] headline: layered {args.n}^2 p=4 FP32 hilbert, setup ...")
-    sim, t_setup = make_sim(sem, wl, "f32", "hilbert")
+    wl = workloads.workload(args.workload, n=args.n)
+    label = f"{args.workload} n={wl.nx} p={wl.p} {args.precision} {args.order} S={wl.n_shots}"
+    log(f"[bench] headline: {label}, setup ...")
+    sim, t_setup = make_sim(sem, wl, args.precision, args.order)
     log(f"[bench] setup {t_setup:.1f} s, timing {args.steps} steps")
     sps, _ = time_steps(torch, sim, args.steps, args.warmup)
-    main_leg = leg_summary(sim, sps, "layered1024 p4 f32 hilbert S=1")
+    main_leg = leg_summary(sim, sps, label)
     log(f"[bench] headline {main_leg['gdof_steps_per_s']:.1f} GDOF*steps/s, {main_leg['us_per_step']:.1f} us/step")
     sim.close()
 
@@ -227,10 +233,11 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": args.precision,
         "data": "synthetic",
-        "config": {"workload": f"layered jittered {args.n}x{args.n} quads, p=4, six layers 1500-4500 m/s "
-                               f"+-5%, Ricker 15 Hz at centre, 128 receivers, Hilbert order, 1 shot",
+        "config": {"workload": (f"layered jittered {wl.nx}x{wl.nx} quads, p=4, six layers 1500-4500 m/s "
+                                f"+-5%, Ricker 15 Hz at centre, 128 receivers, {args.order} order, 1 shot")
+                   if args.workload == "layered1024" else label,
                    "n_nodes": main_leg["n_nodes"], "n_elements": main_leg["n_elements"],
                    "tile_elems": main_leg["tile_elems"], "parallelism": "1 GPU"},
         "roofline": {"bound": "hbm", "achieved": main_leg["achieved_GBs"], "peak": HBM_PEAK_GBS,

@@ -244,13 +244,18 @@ __global__ void __launch_bounds__(kBlock, sizeof(T) == 8 ? SEM_MIN_WAVES_F64 : S
         const bool pair = own && a.grad != nullptr;
         T dot = T(0);
         // scatter the owned entries into LDS. The node ids are re-read here (cache hits)
-        // rather than kept live through the contraction.
+        // rather than kept live through the contraction. Element-interior nodes belong to
+        // this element alone (plain store); edge and corner nodes are shared (atomics).
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
             const int node = bload<int>(r_conn, eoff + q * 256);
             if (pair) dot += r[q] * bload<T>(r_pair, (uint32_t)node * ustride + soff);
             const int loc = node - nb;
-            if ((unsigned)loc < (unsigned)nown) atomicAdd(&acc[loc * SL + s], c2 * r[q]);
+            const int qa = q % N, qb = q / N;
+            if ((unsigned)loc < (unsigned)nown) {
+                if (qa > 0 && qa < P && qb > 0 && qb < P) acc[loc * SL + s] = c2 * r[q];
+                else atomicAdd(&acc[loc * SL + s], c2 * r[q]);
+            }
         }
         if (a.grad != nullptr) {
             // every lane of an SL-group is active together (items are SL-aligned)
@@ -488,10 +493,16 @@ step_rows_kernel(const StepArgs<T> a) {
                     dot += r[aa] * bload<T>(r_pair, (uint32_t)idx[pp][aa] * (uint32_t)sizeof(T));
                 atomicAdd(&a.grad[e], (double)dot);
             }
+            // Element-interior nodes (0 < a, j < p) belong to this element alone: a plain
+            // LDS store; nodes on element edges and corners are shared and need atomics.
+            const bool inner_row = j > 0 && j < P;
 #pragma unroll
             for (int aa = 0; aa < N; ++aa) {
                 const int loc = idx[pp][aa] - nb;
-                if ((unsigned)loc < (unsigned)nown) atomicAdd(&acc[loc], bl[pp][6] * r[aa]);
+                if ((unsigned)loc < (unsigned)nown) {
+                    if (aa > 0 && aa < P && inner_row) acc[loc] = bl[pp][6] * r[aa];
+                    else atomicAdd(&acc[loc], bl[pp][6] * r[aa]);
+                }
             }
         }
     }
