@@ -76,9 +76,14 @@ typedef struct {
     double cfl;              /* CFL number of the default dt; 0 = 0.3                  */
     void* stream;            /* hipStream_t for all device work; NULL = default stream */
     int32_t tile_elems;      /* > 0: fixed tiles of this many elements; 0 = adaptive     */
-    int32_t shot_lanes;      /* shots per element inside a workgroup; 0 = automatic     */
+    int32_t shot_lanes;      /* shots per element inside a workgroup; 0 = automatic     *
+                              * (64 when n_shots % 64 == 0: one wave per element, one    *
+                              * shot per lane)                                          */
     int32_t tile_items;      /* adaptive tiles: own + halo elements per tile; 0 = auto  */
-    int32_t block_threads;   /* single-shot workgroup size 256/512/1024; 0 = automatic  */
+    int32_t block_threads;   /* workgroup size 256/512/1024 of the single-shot and the  *
+                              * 64-shot kernels; 0 = automatic                          */
+    int32_t lds_bytes;       /* LDS budget of a tile's owned-node accumulator, bytes,    *
+                              * <= 163840; 0 = automatic                                */
 } sem_options;
 
 typedef struct {
@@ -105,6 +110,10 @@ typedef struct {
     double alg_flops_per_step;
     double setup_seconds;    /* host setup wall time (numbering, reorder, geometry)   */
     double reorder_seconds;  /* part of setup spent on element and node reordering    */
+    int32_t max_accum_nodes; /* LDS accumulator slots of the largest tile: its owned   *
+                              * nodes, or with 64 shot lanes its owned nodes of two or *
+                              * more elements (each tile's owned range lists those     *
+                              * first, then the nodes of a single element)             */
 } sem_info;
 
 /* Build the context: validate the mesh, number the GLL nodes, reorder elements and

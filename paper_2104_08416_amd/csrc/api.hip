@@ -31,14 +31,14 @@ struct sem_ctx {
     sem::MeshIn mesh;                 // pointers valid only during sem_create
     int precision = SEM_F32;
     int S = 1, SL = 1;
-    int geo = 0;                      // 1: geometric factors computed in-kernel
+    int geo = 0;                      // kernel code of sem::launch_step (0: shot-batch kernel)
     int device = -1;
     bool host_only = true;
     hipStream_t stream = nullptr;
     std::string err;
     size_t wsize = 4;                 // bytes per state word
     // device mesh/tiling
-    DevBuf conn, G, c2, dtminv, tile_eb, tile_nb, halo_b, halo, n2o_node, n2o_elem;
+    DevBuf conn, G, c2, dtminv, tile_eb, tile_nb, tile_ns, halo_b, halo, n2o_node, n2o_elem;
     // state
     DevBuf u[2], v;
     int cur = 0;
@@ -70,7 +70,7 @@ int fail(sem_ctx* c, int code, const std::string& msg) {
 }
 
 hipError_t dev_alloc(DevBuf& b, size_t bytes) {
-    if (b.p) { hipFree(b.p); b.p = nullptr; b.bytes = 0; }
+    if (b.p) { (void)hipFree(b.p); b.p = nullptr; b.bytes = 0; }
     if (bytes == 0) return hipSuccess;
     hipError_t e = hipMalloc(&b.p, bytes);
     if (e == hipSuccess) b.bytes = bytes;
@@ -78,7 +78,7 @@ hipError_t dev_alloc(DevBuf& b, size_t bytes) {
 }
 
 void dev_free(DevBuf& b) {
-    if (b.p) hipFree(b.p);
+    if (b.p) (void)hipFree(b.p);
     b.p = nullptr;
     b.bytes = 0;
 }
@@ -123,6 +123,7 @@ sem::StepArgs<T> base_args(sem_ctx* c) {
     // bounds of the buffer-resource reads of dt/M use the same byte count as the state
     a.tile_eb = (const int32_t*)c->tile_eb.p;
     a.tile_nb = (const int32_t*)c->tile_nb.p;
+    a.tile_ns = (const int32_t*)c->tile_ns.p;
     a.halo_b = (const int32_t*)c->halo_b.p;
     a.halo = (const int32_t*)c->halo.p;
     a.n_slices = c->S / c->SL;
@@ -139,7 +140,12 @@ sem::StepArgs<T> base_args(sem_ctx* c) {
     return a;
 }
 
-size_t lds_bytes(const sem_ctx* c) { return (size_t)c->plan.max_owned * c->SL * c->wsize; }
+// accumulator bytes of the largest tile: all owned nodes, or (64-shot kernel) the owned
+// nodes of two or more elements
+size_t lds_bytes(const sem_ctx* c) {
+    const int32_t slots = c->geo >= sem::kGeoShots ? c->plan.max_shared : c->plan.max_owned;
+    return (size_t)slots * c->SL * c->wsize;
+}
 
 template <typename T>
 int launch(sem_ctx* c, const sem::StepArgs<T>& a) {
@@ -250,14 +256,34 @@ int set_device(sem_ctx* c) {
     return SEM_OK;
 }
 
+bool shots_kernel(const sem_ctx* c) { return c->geo >= sem::kGeoShots; }
+bool row_kernel(const sem_ctx* c) { return c->geo > 0 && c->geo < sem::kGeoShots; }
+
 // Element arrays in the layout of the context's kernel: the single-shot row kernel reads
 // element-major records (node ids [E][nq]; [E][8] = bilinear coefficients, c^2, 0); the
-// shot-batch kernel reads 64-element blocks ([E/64][nq][64] ids, [E/64][3][nq][64] factors).
+// 64-shot kernel reads element-major ids [E][nq] and factors [E][3 nq + 1] (g11, g12, g22
+// per node, then c^2); the shot-batch kernel reads 64-element blocks ([E/64][nq][64] ids,
+// [E/64][3][nq][64] factors).
 template <typename T>
 int upload_geometry(sem_ctx* c) {
     const sem::Plan& P = c->plan;
     const int64_t nq = P.nq, ne = P.ne;
-    if (c->geo) {
+    if (shots_kernel(c)) {
+        const int64_t rec = 3 * nq + 1;
+        std::vector<int32_t> cb((size_t)ne * nq);
+        std::vector<double> gb((size_t)ne * rec);
+        for (int64_t e = 0; e < ne; ++e) {
+            for (int64_t q = 0; q < nq; ++q) {
+                cb[e * nq + q] = P.conn_soa[q * ne + e];
+                for (int64_t k = 0; k < 3; ++k) gb[e * rec + k * nq + q] = P.G_soa[(k * nq + q) * ne + e];
+            }
+            gb[e * rec + 3 * nq] = P.c2[e];
+        }
+        SEM_HIP(c, upload(c, c->conn, cb));
+        SEM_HIP(c, upload_real(c, c->G, gb));
+        return SEM_OK;
+    }
+    if (row_kernel(c)) {
         std::vector<int32_t> cb((size_t)ne * nq);
         std::vector<double> gb((size_t)ne * 8, 0.0);
         for (int64_t e = 0; e < ne; ++e) {
@@ -294,6 +320,7 @@ int upload_mesh(sem_ctx* c) {
     SEM_HIP(c, upload_real(c, c->dtminv, P.minv, P.dt));
     SEM_HIP(c, upload(c, c->tile_eb, P.tile_eb));
     SEM_HIP(c, upload(c, c->tile_nb, P.tile_nb));
+    if (!P.tile_ns.empty()) SEM_HIP(c, upload(c, c->tile_ns, P.tile_ns));
     SEM_HIP(c, upload(c, c->halo_b, P.halo_b));
     std::vector<int32_t> h = P.halo;
     if (h.empty()) h.push_back(0);
@@ -308,6 +335,7 @@ int upload_mesh(sem_ctx* c) {
 
 int pick_shot_lanes(int S, int requested) {
     if (requested > 0) return requested;
+    if (S % 64 == 0) return 64;                   // the 64-shot kernel (one wave per element)
     int sl = 1;
     while (sl < 16 && S % (sl * 2) == 0) sl *= 2;
     return sl;
@@ -322,9 +350,13 @@ int pick_tile_items(int p, int sl, int row_block, int requested) {
     return sl == 1 ? (64 / (p + 1)) * (row_block / 64) : 4 * sem::kBlock / sl;
 }
 
-int pick_max_owned(int sl, int precision) {
+// Accumulator slots per tile: the LDS accumulator [slots][shot_lanes] fills lds_budget
+// bytes (default 64 KB; 64-shot kernel 32 KB, several workgroups per CU).
+int pick_max_owned(int sl, int precision, int lds_budget) {
     const int word = precision == SEM_F64 ? 8 : 4;
-    return 65536 / (sl * word);
+    int budget = lds_budget;
+    if (budget <= 0) budget = sl == 64 ? 32 * 1024 : 65536;
+    return budget / (sl * word);
 }
 
 // owning tile of a new node id
@@ -627,12 +659,31 @@ int sem_create(const sem_mesh* mesh, const sem_options* opt, sem_ctx** out) {
     // passes of the row kernel whose loads are batched: enough to cover one tile, <= 4
     const int epb = (64 / (opt->p + 1)) * (row_block / 64);
     const int max_np = row_block == 256 ? 4 : (row_block == 512 ? 2 : 1);
+    if (opt->lds_bytes < 0 || opt->lds_bytes > 160 * 1024) {
+        g_create_error = "lds_bytes must be in 0..163840";
+        delete c;
+        return SEM_ERR_INVALID_ARG;
+    }
     po.tile_items = pick_tile_items(opt->p, c->SL, row_block, opt->tile_items);
     if (opt->tile_items <= 0 && c->SL == 1) po.tile_items = epb;
+    // 64 shots: tiles are bounded by the LDS accumulator, not by an element count
+    if (opt->tile_items <= 0 && c->SL == 64) po.tile_items = 1 << 20;
     int np = 1;
     while (np < max_np && np * epb < (opt->tile_elems > 0 ? opt->tile_elems : po.tile_items)) np *= 2;
-    po.max_owned = pick_max_owned(c->SL, opt->precision);
-    c->geo = c->S == 1 ? row_block * 8 + np : 0;     // single shot: row kernel, in-kernel geometry
+    po.max_owned = pick_max_owned(c->SL, opt->precision, opt->lds_bytes);
+    po.split_single = c->S > 1 && c->SL == 64;
+    if (po.max_owned < 1) {
+        g_create_error = "lds_bytes too small for one owned node";
+        delete c;
+        return SEM_ERR_INVALID_ARG;
+    }
+    // single shot: row kernel with in-kernel geometry; 64-shot lanes: one wave per element
+    if (c->S == 1) c->geo = row_block * 8 + np;
+    // 64 shots: FP32 1024 threads (100 VGPRs at p = 4, four waves per SIMD), FP64 512
+    // threads (140 VGPRs; 1024 would spill)
+    else if (c->SL == 64)
+        c->geo = sem::kGeoShots + (opt->block_threads > 0 ? row_block : (opt->precision == SEM_F64 ? 512 : 1024));
+    else c->geo = 0;
     int code = SEM_OK;
     std::string err;
     try {
@@ -650,6 +701,17 @@ int sem_create(const sem_mesh* mesh, const sem_options* opt, sem_ctx** out) {
         return code;
     }
     c->setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (!c->host_only && !row_kernel(c) && lds_bytes(c) > 160 * 1024) {
+        g_create_error = "owned nodes x shot lanes of the largest tile exceed the 160 KB of LDS "
+                         "(use smaller tile_elems)";
+        delete c;
+        return SEM_ERR_INVALID_ARG;
+    }
+    if (!c->host_only && (double)c->plan.nn * c->S * c->wsize >= 4294967296.0) {
+        g_create_error = "n_nodes * n_shots * word size must stay below 4 GiB (32-bit buffer offsets)";
+        delete c;
+        return SEM_ERR_INVALID_ARG;
+    }
     if (!c->host_only) {
         int rc = set_device(c);
         if (rc == SEM_OK) rc = c->precision == SEM_F64 ? upload_mesh<double>(c) : upload_mesh<float>(c);
@@ -685,8 +747,8 @@ int sem_get_info(const sem_ctx* c, sem_info* info) {
     info->shot_lanes = c->SL;
     info->max_owned_nodes = P.max_owned;
     info->tile_items = P.tile_items;
-    info->geometry_on_the_fly = c->geo ? 1 : 0;
-    info->block_threads = c->geo ? c->geo / 8 : sem::kBlock;
+    info->geometry_on_the_fly = row_kernel(c) ? 1 : 0;
+    info->block_threads = shots_kernel(c) ? c->geo - sem::kGeoShots : row_kernel(c) ? c->geo / 8 : sem::kBlock;
     info->n_tiles = P.tile_eb.empty() ? 0 : (int64_t)P.tile_eb.size() - 1;
     info->halo_elements = (int64_t)P.halo.size();
     info->step = c->step;
@@ -694,13 +756,11 @@ int sem_get_info(const sem_ctx* c, sem_info* info) {
     info->dt_stable = c->dt_stable;
     info->lambda_max = c->lambda_max;
     const double w = (double)c->wsize, nq = (double)P.nq;
-    // algorithmic bytes: per element nq indices + 3 nq geometric factors + c2; per node
-    // dt/M plus read u, v and write u, v for every shot
     // algorithmic bytes: per element nq node indices, the geometry (6 bilinear-map
     // coefficients when computed in-kernel, else 3 nq stored factors) and c2; per node
     // dt/M plus read u, v and write u, v for every shot
     // (row kernel: one 8-word record holding the 6 coefficients, c2 and padding)
-    const double elem_words = c->geo ? 8.0 : 3.0 * nq + 1.0;
+    const double elem_words = row_kernel(c) ? 8.0 : 3.0 * nq + 1.0;
     info->alg_bytes_per_step = (double)P.ne * (nq * 4.0 + elem_words * w) +
                                (double)P.nn * (w + 4.0 * w * c->S);
     const double n = (double)P.n;
@@ -708,6 +768,7 @@ int sem_get_info(const sem_ctx* c, sem_info* info) {
                                (double)P.nn * c->S * 4.0;
     info->setup_seconds = c->setup_seconds;
     info->reorder_seconds = P.reorder_seconds;
+    info->max_accum_nodes = P.tile_ns.empty() ? P.max_owned : P.max_shared;
     return SEM_OK;
 }
 
@@ -868,9 +929,9 @@ const char* sem_last_error(const sem_ctx* c) {
 void sem_destroy(sem_ctx* c) {
     if (!c) return;
     if (!c->host_only) {
-        hipSetDevice(c->device);
-        hipStreamSynchronize(c->stream);
-        DevBuf* bufs[] = {&c->conn, &c->G, &c->c2, &c->dtminv, &c->tile_eb, &c->tile_nb, &c->halo_b,
+        (void)hipSetDevice(c->device);
+        (void)hipStreamSynchronize(c->stream);
+        DevBuf* bufs[] = {&c->conn, &c->G, &c->c2, &c->dtminv, &c->tile_eb, &c->tile_nb, &c->tile_ns, &c->halo_b,
                           &c->halo, &c->n2o_node, &c->n2o_elem, &c->u[0], &c->u[1], &c->v,
                           &c->src_b, &c->src_loc, &c->src_shot, &c->src_w, &c->rec_b, &c->rec_loc,
                           &c->rec_idx};

@@ -9,6 +9,7 @@ namespace sem {
 
 constexpr int kBlock = 256;     // threads per workgroup of the shot-batch and utility kernels
 constexpr int kRowBlock = 1024; // largest workgroup of the single-shot row kernel
+constexpr int kGeoShots = 1 << 16; // `geo` of the 64-shot kernel: kGeoShots + threads
 constexpr int kMaxP = 7;
 
 // Arguments of the fused step kernel. All arrays use the new (curve) numbering.
@@ -29,6 +30,8 @@ struct StepArgs {
     // tiling
     const int32_t* tile_eb;   // [T+1] element range of each tile
     const int32_t* tile_nb;   // [T+1] owned node range of each tile
+    const int32_t* tile_ns;   // [T] 64-shot kernel: owned nodes of two or more elements
+                              //     (the first tile_ns[t] of the range; the rest have one)
     const int32_t* halo_b;    // [T+1]
     const int32_t* halo;      // halo elements of all tiles
     int32_t n_slices;         // S / shot_lanes
@@ -67,7 +70,9 @@ struct StepArgs {
 
 // geo = threads * 8 + passes (threads 256/512/1024, passes 1/2/4 batched per round of
 // loads): single-shot row kernel, geometric factors computed in-kernel (shot_lanes 1);
-// geo = 0: shot-batch kernel.
+// geo = kGeoShots + threads (256/512/1024): 64-shot kernel, one wave per element
+// (shot_lanes 64, conn [E][nq], G [E][3 nq + 1] = g11, g12, g22 per node, then c^2);
+// geo = 0: general shot-batch kernel.
 // lds_bytes is the owned-node accumulator, the launcher adds the row kernel's stage.
 // Elements per workgroup pass of the row kernel: (64 / (p+1)) * (threads / 64).
 template <typename T>

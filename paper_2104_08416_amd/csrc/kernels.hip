@@ -323,6 +323,211 @@ __global__ void __launch_bounds__(kBlock, sizeof(T) == 8 ? SEM_MIN_WAVES_F64 : S
 }
 
 // ---------------------------------------------------------------------------------------
+// Shot batches of 64: one wave per element, lane = shot. The element's node ids, its
+// stored geometric factors and c^2 are wave-uniform and read with scalar loads (constant
+// address space), so they live in SGPRs; the gathers read one contiguous 64-shot row per
+// node and the LDS accumulator [owned node][64 shots] is hit by 64 consecutive words per
+// instruction (no bank conflicts).
+template <typename T>
+using cptr = const __attribute__((address_space(4))) T*;
+
+template <typename T>
+__device__ __forceinline__ cptr<T> as_const(const T* p) {
+    return (cptr<T>)p;
+}
+
+template <typename T, int P, int BT>
+__global__ void __launch_bounds__(BT) step_shots_kernel(const StepArgs<T> a) {
+    constexpr int N = P + 1, NQ = N * N, SL = 64, NW = BT / 64;
+    constexpr int REC = 3 * NQ + 1;                    // g11[nq] g12[nq] g22[nq] c2
+    constexpr int U = 4;                               // nodes per wave per update round
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* acc = reinterpret_cast<T*>(smem_raw);            // [shared owned][64]
+
+    const int logical = xcd_logical_block();
+    const int tile = logical / a.n_slices;
+    const int s0 = (logical - tile * a.n_slices) * SL;
+    const int nb = a.tile_nb[tile];
+    const int nown = a.tile_nb[tile + 1] - nb;
+    const int ns = a.tile_ns[tile];                     // owned nodes of >= 2 elements
+    const int eb = a.tile_eb[tile];
+    const int n_own_el = a.tile_eb[tile + 1] - eb;
+    const int hb = a.halo_b[tile];
+    const int n_items = n_own_el + (a.halo_b[tile + 1] - hb);
+    const int S = a.S;
+    const cptr<int32_t> conn = as_const(a.conn);
+    const cptr<T> G = as_const(a.G);
+    const cptr<int32_t> halo = as_const(a.halo);
+    const cptr<T> dtminv = as_const(a.dtminv);
+    const rsrc_t r_u = make_rsrc(a.u_in, a.state_bytes);
+    const rsrc_t r_pair = make_rsrc(a.u_pair, a.u_pair ? a.state_bytes : 0u);
+    const uint32_t ustride = (uint32_t)S * (uint32_t)sizeof(T);
+    // this tile's point sources and receivers (per-tile lists, usually empty)
+    const int sb = a.src_b ? a.src_b[tile] : 0, se = a.src_b ? a.src_b[tile + 1] : 0;
+    const int rb = a.rec_b ? a.rec_b[tile] : 0, re = a.rec_b ? a.rec_b[tile + 1] : 0;
+    const T amp = se > sb ? (T)ricker(a.src_t, a.f0, a.t0) : T(0);
+
+    for (int i = threadIdx.x; i < ns * SL; i += BT) acc[i] = T(0);
+    __syncthreads();
+
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const uint32_t soff = (uint32_t)(s0 + lane) * (uint32_t)sizeof(T);
+    for (int k = wave; k < n_items; k += NW) {
+        const bool own = k < n_own_el;
+        const int e = own ? eb + k : halo[hb + k - n_own_el];
+        const cptr<int32_t> ce = conn + (int64_t)e * NQ;
+        const cptr<T> ge = G + (int64_t)e * REC;
+        T u[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) u[q] = bload<T>(r_u, (uint32_t)ce[q] * ustride + soff);
+        T r[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) r[q] = T(0);
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            T f1[N], f2[N];
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                T gx = T(0), gy = T(0);
+#pragma unroll
+                for (int m = 0; m < N; ++m) {
+                    gx += a.D[i * N + m] * u[m + N * j];
+                    gy += a.D[j * N + m] * u[i + N * m];
+                }
+                const int q = i + N * j;
+                const T g11 = ge[q], g12 = ge[NQ + q], g22 = ge[2 * NQ + q];
+                f1[i] = g11 * gx + g12 * gy;
+                f2[i] = g12 * gx + g22 * gy;
+            }
+#pragma unroll
+            for (int aa = 0; aa < N; ++aa) {
+                T s1 = r[aa + N * j];
+#pragma unroll
+                for (int i = 0; i < N; ++i) s1 += a.D[i * N + aa] * f1[i];
+                r[aa + N * j] = s1;
+            }
+#pragma unroll
+            for (int bb = 0; bb < N; ++bb) {
+#pragma unroll
+                for (int aa = 0; aa < N; ++aa) r[aa + N * bb] += a.D[j * N + bb] * f2[aa];
+            }
+        }
+        const T c2 = ge[3 * NQ];
+        if (a.grad != nullptr && own) {
+            T dot = T(0);
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) dot += r[q] * bload<T>(r_pair, (uint32_t)ce[q] * ustride + soff);
+            dot = group_sum<64>(dot);
+            if (lane == 0) atomicAdd(&a.grad[e], (double)dot);
+        }
+        // Node ids are wave-uniform, so these branches do not diverge. Nodes of several
+        // elements accumulate in LDS; a node of this element alone is finished here.
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int node = ce[q];
+            const int loc = node - nb;
+            if ((unsigned)loc < (unsigned)ns) {
+                atomicAdd(&acc[loc * SL + lane], c2 * r[q]);
+            } else if (own && (unsigned)loc < (unsigned)nown) {
+                // point sources and injected residuals at such nodes are added after
+                // the element loop, as corrections of v and u
+                const T rt = c2 * r[q];
+                const int64_t g = (int64_t)node * S + s0 + lane;
+                if (a.mode == 0) {
+                    const T vn = a.v[g] - dtminv[node] * rt;
+                    a.v[g] = vn;
+                    a.u_out[g] = u[q] + a.dt * vn;
+                } else {
+                    a.r_out[g] = a.mode == 2 ? dtminv[node] * rt : rt;
+                }
+            }
+        }
+    }
+    __syncthreads();
+
+    // Sources and adjoint injection: force f enters as acc -= f at accumulated nodes; at
+    // single-element nodes (already advanced without it) as v += dt/M f, u += dt dt/M f,
+    // with global atomics (several receivers may sit on one node).
+    if (se > sb) {
+        for (int i = sb + threadIdx.x; i < se; i += BT) {
+            const int sh = a.src_shot[i] - s0, loc = a.src_loc[i];
+            if ((unsigned)sh >= (unsigned)SL) continue;
+            const T f = a.src_w[i] * amp;
+            if (loc < ns) {
+                atomicAdd(&acc[loc * SL + sh], -f);
+            } else {
+                const int64_t g = (int64_t)(nb + loc) * S + s0 + sh;
+                const T dv = a.dtminv[nb + loc] * f;
+                atomicAdd(&a.v[g], dv);
+                atomicAdd(&a.u_out[g], a.dt * dv);
+            }
+        }
+        __syncthreads();
+    }
+    if (a.inj != nullptr && re > rb) {
+        for (int i = threadIdx.x; i < (re - rb) * SL; i += BT) {
+            const int kk = rb + i / SL, sh = i % SL, loc = a.rec_loc[kk];
+            const T f = a.inj[((int64_t)(s0 + sh) * a.n_rec + a.rec_idx[kk]) * a.inj_cols + a.inj_col] *
+                        a.inj_scale;
+            if (loc < ns) {
+                atomicAdd(&acc[loc * SL + sh], -f);
+            } else {
+                const int64_t g = (int64_t)(nb + loc) * S + s0 + sh;
+                const T dv = a.dtminv[nb + loc] * f;
+                atomicAdd(&a.v[g], dv);
+                atomicAdd(&a.u_out[g], a.dt * dv);
+            }
+        }
+        __syncthreads();
+    }
+    if (a.mode == 0) {
+        // one wave per accumulated node, U nodes per round with all loads issued first
+        const rsrc_t r_v = make_rsrc(a.v, a.state_bytes);
+        for (int l0 = wave; l0 < ns; l0 += NW * U) {
+            T vv[U], uu[U], mm[U], ac[U];
+#pragma unroll
+            for (int t = 0; t < U; ++t) {
+                const int loc = l0 + t * NW;
+                const uint32_t off = (uint32_t)(nb + loc) * ustride + soff;
+                vv[t] = bload<T>(r_v, off);
+                uu[t] = bload<T>(r_u, off);
+                mm[t] = loc < ns ? dtminv[nb + loc] : T(0);
+                ac[t] = loc < ns ? acc[loc * SL + lane] : T(0);
+            }
+#pragma unroll
+            for (int t = 0; t < U; ++t) {
+                const int loc = l0 + t * NW;
+                if (loc < ns) {
+                    const int64_t g = (int64_t)(nb + loc) * S + s0 + lane;
+                    const T vn = vv[t] - mm[t] * ac[t];
+                    a.v[g] = vn;
+                    const T un = uu[t] + a.dt * vn;
+                    a.u_out[g] = un;
+                    acc[loc * SL + lane] = un;
+                }
+            }
+        }
+        if (a.trace != nullptr && re > rb) {
+            __syncthreads();
+            for (int i = threadIdx.x; i < (re - rb) * SL; i += BT) {
+                const int kk = rb + i / SL, sh = i % SL, loc = a.rec_loc[kk];
+                // single-element nodes: read back from L2 (the corrections above are atomics)
+                a.trace[((int64_t)(s0 + sh) * a.n_rec + a.rec_idx[kk]) * a.trace_cols + a.trace_col] =
+                    loc < ns ? acc[loc * SL + sh]
+                             : __hip_atomic_load(&a.u_out[(int64_t)(nb + loc) * S + s0 + sh], __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+    } else {
+        for (int loc = wave; loc < ns; loc += NW) {
+            const int64_t g = (int64_t)(nb + loc) * S + s0 + lane;
+            a.r_out[g] = a.mode == 2 ? dtminv[nb + loc] * acc[loc * SL + lane] : acc[loc * SL + lane];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------
 // Single-shot step, one thread per element row. p+1 consecutive lanes of a wave hold the
 // p+1 rows (second reference index j) of one element; a wave holds 64/(p+1) elements and
 // a 1024-thread workgroup 16 times that. The two contractions that run across rows (the
@@ -579,8 +784,29 @@ hipError_t launch_rows(int64_t n_tiles, size_t lds, const StepArgs<T>& a, hipStr
     return hipGetLastError();
 }
 
+template <typename T, int P, int BT>
+hipError_t launch_shots(int64_t n_tiles, size_t lds, const StepArgs<T>& a, hipStream_t st) {
+    auto fn = step_shots_kernel<T, P, BT>;
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(fn, dim3((unsigned)(n_tiles * a.n_slices)), dim3(BT), lds, st, a);
+    return hipGetLastError();
+}
+
 template <typename T, int P>
 hipError_t launch_p(int sl, int geo, int64_t nt, size_t lds, const StepArgs<T>& a, hipStream_t st) {
+    if (geo >= kGeoShots) {
+        if (sl != 64) return hipErrorInvalidValue;
+        switch (geo - kGeoShots) {
+            case 256: return launch_shots<T, P, 256>(nt, lds, a, st);
+            case 512: return launch_shots<T, P, 512>(nt, lds, a, st);
+            case 1024: return launch_shots<T, P, 1024>(nt, lds, a, st);
+            default: return hipErrorInvalidValue;
+        }
+    }
     if (geo) {
         if (sl != 1) return hipErrorInvalidValue;
         // geo = threads per workgroup * 8 + passes batched per round of loads
@@ -601,7 +827,6 @@ hipError_t launch_p(int sl, int geo, int64_t nt, size_t lds, const StepArgs<T>& 
         case 8: return launch_one<T, P, 8, 0>(nt, lds, a, st);
         case 16: return launch_one<T, P, 16, 0>(nt, lds, a, st);
         case 32: return launch_one<T, P, 32, 0>(nt, lds, a, st);
-        case 64: return launch_one<T, P, 64, 0>(nt, lds, a, st);
         default: return hipErrorInvalidValue;
     }
 }

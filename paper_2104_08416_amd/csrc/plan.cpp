@@ -289,7 +289,7 @@ int32_t nearest_node(const Plan& plan, double px, double py) {
     return best;
 }
 
-void build_tiles(Plan& P, int tile_elems, int tile_items, int max_owned) {
+void build_tiles(Plan& P, int tile_elems, int tile_items, int max_owned, bool split_single) {
     const int64_t ne = P.ne, nq = P.nq;
     // node -> incident elements (new numbering)
     std::vector<int32_t> n2e_b(P.nn + 1, 0), n2e((size_t)ne * nq);
@@ -301,6 +301,10 @@ void build_tiles(Plan& P, int tile_elems, int tile_items, int max_owned) {
             for (int64_t e = 0; e < ne; ++e) n2e[fill[P.conn_soa[q * ne + e]]++] = (int32_t)e;
     }
     auto node_of = [&](int64_t e, int64_t q) { return P.conn_soa[q * ne + e]; };
+    // counted[v] = number of nodes below v that occupy an accumulator slot
+    std::vector<int64_t> counted(P.nn + 1, 0);
+    for (int64_t v = 0; v < P.nn; ++v)
+        counted[v + 1] = counted[v] + ((!split_single || n2e_b[v + 1] - n2e_b[v] > 1) ? 1 : 0);
     P.tile_elems = tile_elems > 0 ? tile_elems : 0;
     P.tile_items = tile_elems > 0 ? 0 : tile_items;
     P.tile_eb.assign(1, 0);
@@ -336,7 +340,7 @@ void build_tiles(Plan& P, int tile_elems, int tile_items, int max_owned) {
             const int64_t halo_after = halo_count - (was_halo ? 1 : 0) + (int64_t)fresh_halo.size();
             bool stop;
             if (tile_elems > 0) stop = own_after > tile_elems;
-            else stop = e > e0 && (own_after + halo_after > tile_items || new_hi - nb > max_owned);
+            else stop = e > e0 && (own_after + halo_after > tile_items || counted[new_hi] - counted[nb] > max_owned);
             if (stop) {
                 for (int32_t f : fresh_halo) mark[f] = -1;     // undo the tentative marks
                 break;
@@ -359,6 +363,34 @@ void build_tiles(Plan& P, int tile_elems, int tile_items, int max_owned) {
     P.max_owned = 0;
     for (size_t k = 0; k + 1 < P.tile_nb.size(); ++k)
         P.max_owned = std::max<int32_t>(P.max_owned, P.tile_nb[k + 1] - P.tile_nb[k]);
+    P.tile_ns.clear();
+    P.max_shared = P.max_owned;
+    if (!split_single) return;
+    // stable partition of every owned range: shared nodes, then single-element nodes
+    const int64_t nt = (int64_t)P.tile_nb.size() - 1;
+    std::vector<int32_t> perm(P.nn);
+    P.tile_ns.resize(nt);
+    P.max_shared = 0;
+    for (int64_t k = 0; k < nt; ++k) {
+        const int32_t b = P.tile_nb[k], f = P.tile_nb[k + 1];
+        int32_t next = b;
+        for (int32_t v = b; v < f; ++v)
+            if (n2e_b[v + 1] - n2e_b[v] > 1) perm[v] = next++;
+        P.tile_ns[k] = next - b;
+        P.max_shared = std::max<int32_t>(P.max_shared, next - b);
+        for (int32_t v = b; v < f; ++v)
+            if (n2e_b[v + 1] - n2e_b[v] <= 1) perm[v] = next++;
+    }
+    for (auto& v : P.conn_soa) v = perm[v];
+    std::vector<int32_t> n2o(P.nn);
+    std::vector<double> minv(P.nn);
+    for (int64_t v = 0; v < P.nn; ++v) {
+        n2o[perm[v]] = P.node_new2old[v];
+        minv[perm[v]] = P.minv[v];
+    }
+    P.node_new2old.swap(n2o);
+    P.minv.swap(minv);
+    for (int64_t v = 0; v < P.nn; ++v) P.node_old2new[P.node_new2old[v]] = (int32_t)v;
 }
 
 void element_geometry(const Plan& P, const MeshIn& m, int64_t e, double* g11, double* g12,
@@ -563,7 +595,8 @@ std::string build_plan(const MeshIn& m, const PlanOptions& opt, Plan& P, int& co
     }
     P.minv.resize(nn);
     for (int64_t i = 0; i < nn; ++i) P.minv[i] = 1.0 / mass[P.node_new2old[i]];
-    if (opt.node_order == SEM_NODES_FIRST_TOUCH) build_tiles(P, opt.tile_elems, opt.tile_items, opt.max_owned);
+    if (opt.node_order == SEM_NODES_FIRST_TOUCH)
+        build_tiles(P, opt.tile_elems, opt.tile_items, opt.max_owned, opt.split_single);
     code = SEM_OK;
     return "";
 }

@@ -29,6 +29,10 @@ struct PlanOptions {
     int tile_elems = 0;      // > 0: fixed tiles of this many elements
     int tile_items = 256;    // adaptive tiles: own + halo elements per tile at most this
     int max_owned = 1 << 30; // adaptive tiles: owned nodes per tile at most this
+    // Regroup each tile's owned nodes: nodes of two or more elements first, then nodes of
+    // a single element (kept in registers by the 64-shot kernel); max_owned then bounds
+    // the first group only.
+    bool split_single = false;
 };
 
 struct Plan {
@@ -56,6 +60,10 @@ struct Plan {
     int tile_items = 0;                      // adaptive cap on own + halo elements
     std::vector<int32_t> tile_eb, tile_nb, halo_b, halo;
     int32_t max_owned = 0;
+    // split_single: tile t's owned nodes [tile_nb[t], tile_nb[t] + tile_ns[t]) belong to
+    // two or more elements, the rest of its range to exactly one (an own element).
+    std::vector<int32_t> tile_ns;
+    int32_t max_shared = 0;
     double reorder_seconds = 0.0;
 };
 
@@ -64,8 +72,9 @@ std::string build_plan(const MeshIn& mesh, const PlanOptions& opt, Plan& plan, i
 
 // (Re)build the tiling: fixed tiles of `tile_elems` elements when > 0, else adaptive tiles
 // that grow along the element order while own + halo elements <= tile_items and owned
-// nodes <= max_owned.
-void build_tiles(Plan& plan, int tile_elems, int tile_items, int max_owned);
+// nodes (with split_single: owned nodes of two or more elements) <= max_owned.
+// split_single then regroups every tile's owned range and renumbers the nodes.
+void build_tiles(Plan& plan, int tile_elems, int tile_items, int max_owned, bool split_single);
 
 // Cell index along the generalized Hilbert curve over a W x H grid.
 int64_t hilbert_index(int64_t W, int64_t H, int64_t cx, int64_t cy);

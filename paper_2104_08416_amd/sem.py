@@ -41,7 +41,8 @@ class _Options(ctypes.Structure):
                 ("node_order", ctypes.c_int32), ("seed", ctypes.c_uint64), ("n_shots", ctypes.c_int32),
                 ("device", ctypes.c_int32), ("dt", ctypes.c_double), ("cfl", ctypes.c_double),
                 ("stream", ctypes.c_void_p), ("tile_elems", ctypes.c_int32), ("shot_lanes", ctypes.c_int32),
-                ("tile_items", ctypes.c_int32), ("block_threads", ctypes.c_int32)]
+                ("tile_items", ctypes.c_int32), ("block_threads", ctypes.c_int32),
+                ("lds_bytes", ctypes.c_int32)]
 
 
 class _Info(ctypes.Structure):
@@ -54,7 +55,8 @@ class _Info(ctypes.Structure):
                 ("n_tiles", ctypes.c_int64), ("halo_elements", ctypes.c_int64), ("step", ctypes.c_int64),
                 ("dt", ctypes.c_double), ("dt_stable", ctypes.c_double), ("lambda_max", ctypes.c_double),
                 ("alg_bytes_per_step", ctypes.c_double), ("alg_flops_per_step", ctypes.c_double),
-                ("setup_seconds", ctypes.c_double), ("reorder_seconds", ctypes.c_double)]
+                ("setup_seconds", ctypes.c_double), ("reorder_seconds", ctypes.c_double),
+                ("max_accum_nodes", ctypes.c_int32)]
 
 
 EXPORTS = ("sem_create", "sem_create_error", "sem_get_info", "sem_get_permutations",
@@ -130,7 +132,8 @@ class Simulator:
     def __init__(self, vxy, quads, c2, p: int, precision: str = "f32", order: str = "hilbert",
                  n_shots: int = 1, dt: float = 0.0, cfl: float = 0.3, device: int = 0,
                  seed: int = 3, node_order: str = "first_touch", tile_elems: int = 0,
-                 shot_lanes: int = 0, tile_items: int = 0, block_threads: int = 0, stream=None):
+                 shot_lanes: int = 0, tile_items: int = 0, block_threads: int = 0,
+                 lds_bytes: int = 0, stream=None):
         self._vxy = np.ascontiguousarray(vxy, dtype=np.float64)
         self._quads = np.ascontiguousarray(quads, dtype=np.int32)
         self._c2 = np.ascontiguousarray(c2, dtype=np.float64)
@@ -146,7 +149,7 @@ class Simulator:
             self._torch_device = torch.device("cuda", device)
         o = _Options(p, F64 if precision == "f64" else F32, ORDERS[order], NODE_ORDERS[node_order],
                      seed, n_shots, device, dt, cfl, stream or 0, tile_elems, shot_lanes, tile_items,
-                     block_threads)
+                     block_threads, lds_bytes)
         h = ctypes.c_void_p()
         rc = _lib.sem_create(ctypes.byref(m), ctypes.byref(o), ctypes.byref(h))
         if rc:

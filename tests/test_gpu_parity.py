@@ -81,6 +81,40 @@ def test_fp64_batched_shots(semlib, gpu_ok, lanes):
     assert rel(tr, tr_o) <= 1e-12
 
 
+@pytest.mark.parametrize("shots,block,lds", [(64, 0, 0), (64, 256, 32768), (128, 1024, 49152)])
+def test_fp64_64_shot_lanes(semlib, gpu_ok, shots, block, lds):
+    """One wave per element with one shot per lane: 64 or 128 shots at seeded positions,
+    FP64, default and small LDS budgets (many tiles, ragged last tile, halos)."""
+    say("case 64-lane shots fp64", shots, block, lds)
+    wl = workloads.workload("batch512", n=24, n_shots=shots, nsteps=300)
+    (tr, u, v), (tr_o, u_o, v_o) = run_both(semlib, wl, wl.nsteps, "f64", "hilbert",
+                                            block_threads=block, lds_bytes=lds)
+    assert rel(u, u_o) <= 1e-12
+    assert rel(v, v_o) <= 1e-12
+    assert rel(tr, tr_o) <= 1e-12
+
+
+def test_64_shot_lanes_selected(semlib, gpu_ok):
+    wl = workloads.workload("batch512", n=16, n_shots=64)
+    s = semlib.Simulator(wl.vxy, wl.quads, wl.c2, wl.p, precision="f32", n_shots=64)
+    inf = s.info()
+    assert inf["shot_lanes"] == 64 and inf["block_threads"] == 1024
+    assert inf["max_accum_nodes"] * 64 * 4 <= 32 * 1024 < inf["max_owned_nodes"] * 64 * 4
+    s.close()
+
+
+def test_apply_stiffness_fp32_64_shots(semlib, gpu_ok):
+    import torch
+    say("case apply fp32 64 shots")
+    wl = workloads.workload("layered1024", n=40)
+    o = solver.SEM(wl.vxy, wl.quads, wl.c2, wl.p)
+    s = semlib.Simulator(wl.vxy, wl.quads, wl.c2, wl.p, precision="f32", n_shots=64)
+    x = workloads.random_field(o.n_nodes, 64, seed=9)
+    r = s.apply_stiffness(torch.tensor(x, dtype=torch.float32, device="cuda")).cpu().numpy()
+    r_o = (o.K @ x.T).T
+    assert rel(r, r_o) <= 2e-6
+
+
 def test_fp32_1000_steps(semlib, gpu_ok):
     """FP32 state and arithmetic against the FP64 oracle after 1000 steps."""
     say("case layered64 fp32 1000 steps")
@@ -139,7 +173,7 @@ def test_resume_from_saved_fields(semlib, gpu_ok):
     assert rel(ua, u_o.T) <= 1e-12
 
 
-def _tiny_inversion(semlib, precision, shots=2, nsteps=80, n=8, p=3):
+def _tiny_inversion(semlib, precision, shots=2, nsteps=80, n=8, p=3, **kw):
     vxy, quads, xc, yc = workloads.grid_mesh(n, n, 800.0, 800.0, jitter=0.2, seed=9)
     c = workloads.layered_c(yc, 800.0, c_top=1500.0, c_step=300.0)
     rng = np.random.default_rng(21)
@@ -147,7 +181,8 @@ def _tiny_inversion(semlib, precision, shots=2, nsteps=80, n=8, p=3):
     c2 = c * c
     o = solver.SEM(vxy, quads, c2_true, p)
     dt = o.dt_cfl()
-    src_xy = np.array([[200.0, 600.0], [560.0, 400.0]])[:shots]
+    src_xy = np.array([[200.0, 600.0], [560.0, 400.0]])[:shots] if shots <= 2 else \
+        np.random.default_rng(22).uniform(0.0, 800.0, size=(shots, 2))
     rec_xy = np.stack([np.linspace(50, 750, 9), np.full(9, 800.0)], 1)
     src = solver.snap_to_nodes(src_xy, o.node_xy)
     rec = solver.snap_to_nodes(rec_xy, o.node_xy)
@@ -155,7 +190,8 @@ def _tiny_inversion(semlib, precision, shots=2, nsteps=80, n=8, p=3):
     obs, _, _ = o.run(nsteps, dt, src, np.arange(shots), f0, rec_nodes=rec, n_shots=shots)
     o.set_c2(c2)
     J, g_o = adjoint.misfit_and_gradient(o, nsteps, dt, src, np.arange(shots), f0, rec, shots, obs)
-    s = semlib.Simulator(vxy, quads, c2, p, precision=precision, n_shots=shots, dt=dt, tile_elems=16)
+    kw = kw or dict(tile_elems=16)
+    s = semlib.Simulator(vxy, quads, c2, p, precision=precision, n_shots=shots, dt=dt, **kw)
     s.set_sources(src_xy, np.arange(shots), f0)
     s.set_receivers(rec_xy)
     return o, s, dict(dt=dt, src=src, rec=rec, f0=f0, obs=obs, J=J, g=g_o, c2=c2, nsteps=nsteps,
@@ -172,6 +208,18 @@ def test_adjoint_gradient_fp64_matches_oracle(semlib, gpu_ok, ckpt):
     J = 0.5 * float((res.double() ** 2).sum())
     assert J == pytest.approx(d["J"], rel=1e-11)
     g = s.adjoint_gradient(res.contiguous(), d["nsteps"], ckpt).cpu().numpy()
+    assert rel(g, d["g"]) <= 1e-10
+
+
+def test_adjoint_gradient_fp64_64_shot_lanes(semlib, gpu_ok):
+    """Gradient pairing of the one-wave-per-element kernel: 64 shots, small tiles."""
+    import torch
+    say("case adjoint fp64 64 shots")
+    o, s, d = _tiny_inversion(semlib, "f64", shots=64, lds_bytes=16384)
+    assert s.info()["shot_lanes"] == 64
+    tr = s.run(d["nsteps"])
+    res = tr - torch.tensor(d["obs"], device="cuda")
+    g = s.adjoint_gradient(res.contiguous(), d["nsteps"], 30).cpu().numpy()
     assert rel(g, d["g"]) <= 1e-10
 
 

@@ -47,6 +47,39 @@ def test_permutations_bit_exact(semlib, name, kw, orders):
         s.close()
 
 
+@pytest.mark.parametrize("name,kw", [("batch512", dict(n=48)), ("graded1414", dict(n=30, p=5))])
+def test_64_shot_lanes_regroup_owned_nodes(semlib, name, kw):
+    """With 64 shot lanes every tile's owned range lists its nodes of two or more elements
+    first, then its nodes of one element, each group in first-touch order; the element
+    order is unchanged and the accumulator slots fit the LDS budget."""
+    wl = workloads.workload(name, **kw)
+    conn, n_nodes = mesh.global_numbering(wl.quads, wl.vxy.shape[0], wl.p)
+    start, _, _ = solver.node_incidence(conn, n_nodes)
+    mult = np.diff(start)
+    oe, on = _oracle_perm(wl, "hilbert")
+    s = semlib.Simulator(wl.vxy, wl.quads, wl.c2, wl.p, device=-1, n_shots=64, lds_bytes=16384)
+    inf = s.info()
+    assert inf["shot_lanes"] == 64
+    assert 0 < inf["max_accum_nodes"] <= 16384 // (64 * 4) < inf["max_owned_nodes"]
+    e, n = s.permutations()
+    s.close()
+    np.testing.assert_array_equal(e, oe)
+    assert np.array_equal(np.sort(n), np.arange(n_nodes)) and not np.array_equal(n, on)
+    pos = np.empty(n_nodes, np.int64)
+    pos[on] = np.arange(n_nodes)              # first-touch position of every node
+    p_lib = pos[n]
+    ends = np.flatnonzero(np.maximum.accumulate(p_lib) == np.arange(n_nodes)) + 1
+    assert len(ends) >= inf["n_tiles"]
+    b = 0
+    for t in ends:
+        blk = n[b:t]
+        shared = mult[blk] > 1
+        k = int(shared.sum())
+        assert shared[:k].all() and not shared[k:].any()
+        assert np.all(np.diff(pos[blk[:k]]) > 0) and np.all(np.diff(pos[blk[k:]]) > 0)
+        b = t
+
+
 @pytest.mark.slow
 def test_permutations_bit_exact_256():
     """65,536 elements, 1,050,625 nodes: a size that spans many tiles."""
