@@ -11,12 +11,26 @@ and single-shot FP64 step on the 512 x 512 mesh, the adjoint-gradient cost ratio
 FP64 CPU oracle on a bounded section of the headline workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--quick] [--legs main,fp64,...]
+       python bench.py --profile-summary DIR --steps K --kernel NAME   (no GPU: turns the
+           rocprofv3 CSV output under DIR into the markdown summaries kept in profiles/)
+
+Roofline fields: ``achieved`` = algorithmic bytes of one step (per element nq int32 ids,
+3 nq geometric factors and c2; per node dt/M and u, v read and written) / the average
+step-kernel duration from HIP events on the kernel's stream. ``traffic`` = FETCH_SIZE +
+WRITE_SIZE bytes per step-kernel dispatch from rocprofv3 counter runs, each scaled by the
+ratio of bytes a plain 1 GiB device copy moves to what the same counter reads for it; it
+is read from the headline summary in profiles/ and is null when the kernel sources have
+changed since those counters were taken.
 """
 from __future__ import annotations
 
 import argparse
+import csv
+import glob
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -27,6 +41,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 ALL_LEGS = ("main", "fp64", "batch", "adjoint", "orders", "cpu")
+KERNEL_SOURCES = ("kernels.hip", "kernels.h", "api.hip", "plan.cpp", "plan.h")
+HEADLINE_PROFILE = os.path.join(ROOT, "profiles", "step_rows_kernel_layered1024_f32_hilbert.md")
+COPY_BYTES = 1 << 30           # the calibration copy reads and writes 1 GiB each
 
 
 def log(*a):
@@ -72,6 +89,9 @@ def leg_summary(sim, sec_per_step, label):
         "alg_bytes_per_step": inf["alg_bytes_per_step"],
         "achieved_GBs": gbs,
         "hbm_frac": gbs / HBM_PEAK_GBS,
+        "kernel_bytes_per_step": inf["kernel_bytes_per_step"],
+        "kernel_bytes_GBs": inf["kernel_bytes_per_step"] / sec_per_step / 1e9,
+        "block_threads": inf["block_threads"],
         "n_nodes": inf["n_nodes"],
         "n_elements": inf["n_elements"],
         "n_shots": inf["n_shots"],
@@ -83,7 +103,112 @@ def leg_summary(sim, sec_per_step, label):
     }
 
 
-def cpu_baseline(n=256, steps=200):
+def sources_sha256():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2104_08416_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def profile_record(path):
+    """The JSON block of a profile summary, or None."""
+    if not os.path.exists(path):
+        return None
+    m = re.search(r"```json\n(.*?)\n```", open(path).read(), re.S)
+    return json.loads(m.group(1)) if m else None
+
+
+def headline_traffic():
+    """FETCH + WRITE bytes per step-kernel dispatch of the headline, if the summary in
+    profiles/ was taken with the current kernel sources."""
+    rec = profile_record(HEADLINE_PROFILE)
+    if rec is None or rec.get("sources_sha256") != sources_sha256():
+        return None
+    return rec["traffic_bytes_per_dispatch"]
+
+
+def _rows(d, pattern):
+    fs = glob.glob(os.path.join(d, "**", pattern), recursive=True)
+    if not fs:
+        raise SystemExit(f"no {pattern} under {d}")
+    with open(fs[0]) as fh:
+        return list(csv.DictReader(fh))
+
+
+def _counter(d, name, kernel, last):
+    vals = [float(r["Counter_Value"]) for r in _rows(d, "*counter_collection.csv")
+            if kernel in r["Kernel_Name"] and r["Counter_Name"] == name]
+    vals = vals[-last:]
+    return sum(vals) / len(vals)
+
+
+def _copy_counter(d, name):
+    rows = [r for r in _rows(d, "*counter_collection.csv")
+            if "copyBuffer" in r["Kernel_Name"] and r["Counter_Name"] == name]
+    top = max(int(r["Grid_Size"]) for r in rows)
+    vals = [float(r["Counter_Value"]) for r in rows if int(r["Grid_Size"]) == top]
+    return sum(vals) / len(vals)
+
+
+def profile_summary(d, kernel, steps, counter_steps):
+    """Markdown summary of rocprofv3 runs under d: trace/ (kernel trace + stats) and, if
+    present, fetch/, write/ (FETCH_SIZE, WRITE_SIZE with the copy calibration) and tcc/
+    (TCC_HIT_sum, TCC_MISS_sum). Averages use the last ``steps`` dispatches of ``kernel``
+    in the trace and the last ``counter_steps`` in the counter runs (the timed steps)."""
+    out = []
+    stats = _rows(os.path.join(d, "trace"), "*kernel_stats.csv")
+    trace = [r for r in _rows(os.path.join(d, "trace"), "*kernel_trace.csv") if kernel in r["Kernel_Name"]]
+    durs = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in trace][-steps:]
+    avg_us = sum(durs) / len(durs)
+    out.append("| kernel | calls | avg us | total % |")
+    out.append("|---|---|---|---|")
+    for r in stats[:8]:
+        out.append(f"| `{r['Name'][:90]}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                   f"{float(r['Percentage']):.1f} |")
+    out.append("")
+    out.append(f"`{kernel}`: last {len(durs)} dispatches (the timed steps) average {avg_us:.1f} us, "
+               f"min {min(durs):.1f}, max {max(durs):.1f}.")
+    rec = {"kernel": kernel, "dispatches": len(durs), "avg_us": avg_us, "sources_sha256": sources_sha256()}
+    if os.path.isdir(os.path.join(d, "fetch")) and os.path.isdir(os.path.join(d, "write")):
+        f_kib = _counter(os.path.join(d, "fetch"), "FETCH_SIZE", kernel, counter_steps)
+        w_kib = _counter(os.path.join(d, "write"), "WRITE_SIZE", kernel, counter_steps)
+        cf = _copy_counter(os.path.join(d, "fetch"), "FETCH_SIZE")
+        cw = _copy_counter(os.path.join(d, "write"), "WRITE_SIZE")
+        fs, ws = COPY_BYTES / (cf * 1024), COPY_BYTES / (cw * 1024)
+        fb, wb = f_kib * 1024 * fs, w_kib * 1024 * ws
+        out.append("")
+        out.append(f"Copy calibration (1 GiB read + 1 GiB written): FETCH_SIZE {cf:.0f} KiB, WRITE_SIZE "
+                   f"{cw:.0f} KiB per dispatch, so scale factors {fs:.3f} (fetch) and {ws:.3f} (write).")
+        out.append(f"`{kernel}` per dispatch: FETCH_SIZE {f_kib:.0f} KiB -> {fb / 1e6:.1f} MB, WRITE_SIZE "
+                   f"{w_kib:.0f} KiB -> {wb / 1e6:.1f} MB, traffic {(fb + wb) / 1e6:.1f} MB.")
+        rec.update({"fetch_kib": f_kib, "write_kib": w_kib, "fetch_scale": fs, "write_scale": ws,
+                    "fetch_bytes_per_dispatch": fb, "write_bytes_per_dispatch": wb,
+                    "traffic_bytes_per_dispatch": fb + wb})
+    if os.path.isdir(os.path.join(d, "tcc")):
+        h = _counter(os.path.join(d, "tcc"), "TCC_HIT_sum", kernel, counter_steps)
+        m = _counter(os.path.join(d, "tcc"), "TCC_MISS_sum", kernel, counter_steps)
+        out.append(f"L2 (TCC) hit rate {h / (h + m):.3f} ({h:.0f} hits, {m:.0f} misses per dispatch).")
+        rec.update({"l2_hit": h / (h + m)})
+    for log_name in ("trace.log", "fetch.log"):
+        lp = os.path.join(d, log_name)
+        if os.path.exists(lp):
+            for line in open(lp):
+                if line.startswith("{"):
+                    b = json.loads(line)
+                    rec.setdefault("bench_us_per_step", b["main"]["us_per_step"])
+                    rec.setdefault("alg_bytes_per_step", b["main"]["alg_bytes_per_step"])
+                    out.append(f"bench.py in the `{log_name[:-4]}` run: {b['main']['us_per_step']:.1f} us/step "
+                               f"(HIP events), {b['main']['alg_bytes_per_step'] / 1e6:.1f} MB algorithmic.")
+                    break
+    out.append("")
+    out.append("```json")
+    out.append(json.dumps(rec, indent=1))
+    out.append("```")
+    return "\n".join(out)
+
+
+def cpu_baseline(n=256, steps=1000):
     """FP64 CPU oracle on an n x n-element section of the layered jittered p=4 workload."""
     import workloads
     from oracle import solver
@@ -125,7 +250,15 @@ def main():
                     help="headline workload (default: the layered 1024^2 p=4 mesh)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
+    ap.add_argument("--profile-summary", default=None, metavar="DIR",
+                    help="summarise rocprofv3 CSV output under DIR (no GPU) and exit")
+    ap.add_argument("--kernel", default="step_rows_kernel", help="kernel of --profile-summary")
+    ap.add_argument("--counter-steps", type=int, default=10,
+                    help="--steps of the counter runs summarised by --profile-summary")
     args = ap.parse_args()
+    if args.profile_summary:
+        print(profile_summary(args.profile_summary, args.kernel, args.steps, args.counter_steps))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); multi-GPU sharding is a "
               "design note, not part of this build.", file=sys.stderr)
@@ -241,7 +374,9 @@ def main():
                    "n_nodes": main_leg["n_nodes"], "n_elements": main_leg["n_elements"],
                    "tile_elems": main_leg["tile_elems"], "parallelism": "1 GPU"},
         "roofline": {"bound": "hbm", "achieved": main_leg["achieved_GBs"], "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": main_leg["hbm_frac"], "traffic": None},
+                     "unit": "GB/s", "frac": main_leg["hbm_frac"],
+                     "traffic": headline_traffic() if (args.workload, args.precision, args.order, args.n)
+                     == ("layered1024", "f32", "hilbert", None) else None},
         "cpu_baseline": cpu,
         "main": main_leg,
     }

@@ -106,7 +106,9 @@ typedef struct {
     double dt;
     double dt_stable;        /* 2/sqrt(lambda_max) from power iteration (0 host-only)  */
     double lambda_max;
-    double alg_bytes_per_step;  /* algorithmic HBM bytes of one step (see DESIGN)     */
+    double alg_bytes_per_step;  /* algorithmic HBM bytes of one step: per element nq   *
+                                 * int32 ids, 3 nq geometric factors and c2; per node *
+                                 * dt/M and, per shot, u and v read and written       */
     double alg_flops_per_step;
     double setup_seconds;    /* host setup wall time (numbering, reorder, geometry)   */
     double reorder_seconds;  /* part of setup spent on element and node reordering    */
@@ -114,6 +116,9 @@ typedef struct {
                               * nodes, or with 64 shot lanes its owned nodes of two or *
                               * more elements (each tile's owned range lists those     *
                               * first, then the nodes of a single element)             */
+    double kernel_bytes_per_step; /* least bytes this context's step kernel reads and   *
+                                   * writes (the single-shot kernel computes geometric *
+                                   * factors from 8 words per element)                 */
 } sem_info;
 
 /* Build the context: validate the mesh, number the GLL nodes, reorder elements and

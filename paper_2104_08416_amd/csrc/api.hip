@@ -756,13 +756,14 @@ int sem_get_info(const sem_ctx* c, sem_info* info) {
     info->dt_stable = c->dt_stable;
     info->lambda_max = c->lambda_max;
     const double w = (double)c->wsize, nq = (double)P.nq;
-    // algorithmic bytes: per element nq node indices, the geometry (6 bilinear-map
-    // coefficients when computed in-kernel, else 3 nq stored factors) and c2; per node
-    // dt/M plus read u, v and write u, v for every shot
-    // (row kernel: one 8-word record holding the 6 coefficients, c2 and padding)
+    // algorithmic bytes of the method: per element nq node indices, 3 nq stored
+    // geometric factors and c2; per node dt/M plus read u, v and write u, v per shot
+    const double per_node = (double)P.nn * (w + 4.0 * w * c->S);
+    info->alg_bytes_per_step = (double)P.ne * (nq * 4.0 + (3.0 * nq + 1.0) * w) + per_node;
+    // what this context's kernel reads at least: the row kernel keeps one 8-word record
+    // per element (6 bilinear-map coefficients, c2, padding) instead of stored factors
     const double elem_words = row_kernel(c) ? 8.0 : 3.0 * nq + 1.0;
-    info->alg_bytes_per_step = (double)P.ne * (nq * 4.0 + elem_words * w) +
-                               (double)P.nn * (w + 4.0 * w * c->S);
+    info->kernel_bytes_per_step = (double)P.ne * (nq * 4.0 + elem_words * w) + per_node;
     const double n = (double)P.n;
     info->alg_flops_per_step = (double)P.ne * c->S * (8.0 * n * n * n + 7.0 * n * n) +
                                (double)P.nn * c->S * 4.0;

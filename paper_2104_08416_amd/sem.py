@@ -56,7 +56,7 @@ class _Info(ctypes.Structure):
                 ("dt", ctypes.c_double), ("dt_stable", ctypes.c_double), ("lambda_max", ctypes.c_double),
                 ("alg_bytes_per_step", ctypes.c_double), ("alg_flops_per_step", ctypes.c_double),
                 ("setup_seconds", ctypes.c_double), ("reorder_seconds", ctypes.c_double),
-                ("max_accum_nodes", ctypes.c_int32)]
+                ("max_accum_nodes", ctypes.c_int32), ("kernel_bytes_per_step", ctypes.c_double)]
 
 
 EXPORTS = ("sem_create", "sem_create_error", "sem_get_info", "sem_get_permutations",
