@@ -269,7 +269,9 @@ int upload_geometry(sem_ctx* c) {
     const sem::Plan& P = c->plan;
     const int64_t nq = P.nq, ne = P.ne;
     if (shots_kernel(c)) {
-        const int64_t rec = 3 * nq + 1;
+        // record: g11, g12, g22 per node, c2, then dt/M at the (p-1)^2 element-interior
+        // nodes (b = 1..p-1 outer, a = 1..p-1 inner)
+        const int64_t ni = (int64_t)(P.p - 1) * (P.p - 1), rec = 3 * nq + 1 + ni;
         std::vector<int32_t> cb((size_t)ne * nq);
         std::vector<double> gb((size_t)ne * rec);
         for (int64_t e = 0; e < ne; ++e) {
@@ -278,6 +280,11 @@ int upload_geometry(sem_ctx* c) {
                 for (int64_t k = 0; k < 3; ++k) gb[e * rec + k * nq + q] = P.G_soa[(k * nq + q) * ne + e];
             }
             gb[e * rec + 3 * nq] = P.c2[e];
+            for (int b = 1; b < P.p; ++b)
+                for (int a2 = 1; a2 < P.p; ++a2) {
+                    const int32_t node = P.conn_soa[(int64_t)(a2 + P.n * b) * ne + e];
+                    gb[e * rec + 3 * nq + 1 + (b - 1) * (P.p - 1) + (a2 - 1)] = P.minv[node] * P.dt;
+                }
         }
         SEM_HIP(c, upload(c, c->conn, cb));
         SEM_HIP(c, upload_real(c, c->G, gb));
@@ -351,11 +358,12 @@ int pick_tile_items(int p, int sl, int row_block, int requested) {
 }
 
 // Accumulator slots per tile: the LDS accumulator [slots][shot_lanes] fills lds_budget
-// bytes (default 64 KB; 64-shot kernel 32 KB, several workgroups per CU).
+// bytes (default 64 KB; 64-shot kernel 32 KB in FP32 and 48 KB in FP64, measured on the
+// 512^2 p=4 batch: several workgroups per CU beat larger tiles with fewer halo elements).
 int pick_max_owned(int sl, int precision, int lds_budget) {
     const int word = precision == SEM_F64 ? 8 : 4;
     int budget = lds_budget;
-    if (budget <= 0) budget = sl == 64 ? 32 * 1024 : 65536;
+    if (budget <= 0) budget = sl == 64 ? (precision == SEM_F64 ? 48 : 32) * 1024 : 65536;
     return budget / (sl * word);
 }
 
@@ -679,10 +687,9 @@ int sem_create(const sem_mesh* mesh, const sem_options* opt, sem_ctx** out) {
     }
     // single shot: row kernel with in-kernel geometry; 64-shot lanes: one wave per element
     if (c->S == 1) c->geo = row_block * 8 + np;
-    // 64 shots: FP32 1024 threads (100 VGPRs at p = 4, four waves per SIMD), FP64 512
-    // threads (140 VGPRs; 1024 would spill)
+    // 64 shots: 256 threads (p = 4: about 100 VGPRs in FP32, 170 in FP64, no spills)
     else if (c->SL == 64)
-        c->geo = sem::kGeoShots + (opt->block_threads > 0 ? row_block : (opt->precision == SEM_F64 ? 512 : 1024));
+        c->geo = sem::kGeoShots + (opt->block_threads > 0 ? row_block : 256);
     else c->geo = 0;
     int code = SEM_OK;
     std::string err;
@@ -762,7 +769,9 @@ int sem_get_info(const sem_ctx* c, sem_info* info) {
     info->alg_bytes_per_step = (double)P.ne * (nq * 4.0 + (3.0 * nq + 1.0) * w) + per_node;
     // what this context's kernel reads at least: the row kernel keeps one 8-word record
     // per element (6 bilinear-map coefficients, c2, padding) instead of stored factors
-    const double elem_words = row_kernel(c) ? 8.0 : 3.0 * nq + 1.0;
+    // (64-shot kernel: stored factors, c2 and dt/M of the (p-1)^2 element-interior nodes)
+    const double elem_words = row_kernel(c) ? 8.0
+                              : 3.0 * nq + 1.0 + (shots_kernel(c) ? (P.p - 1.0) * (P.p - 1.0) : 0.0);
     info->kernel_bytes_per_step = (double)P.ne * (nq * 4.0 + elem_words * w) + per_node;
     const double n = (double)P.n;
     info->alg_flops_per_step = (double)P.ne * c->S * (8.0 * n * n * n + 7.0 * n * n) +

@@ -324,10 +324,10 @@ __global__ void __launch_bounds__(kBlock, sizeof(T) == 8 ? SEM_MIN_WAVES_F64 : S
 
 // ---------------------------------------------------------------------------------------
 // Shot batches of 64: one wave per element, lane = shot. The element's node ids, its
-// stored geometric factors and c^2 are wave-uniform and read with scalar loads (constant
-// address space), so they live in SGPRs; the gathers read one contiguous 64-shot row per
-// node and the LDS accumulator [owned node][64 shots] is hit by 64 consecutive words per
-// instruction (no bank conflicts).
+// stored geometric factors, c^2 and the dt/M of its interior nodes are wave-uniform: they
+// are read with one word per lane and broadcast with readlane. The gathers read one
+// contiguous 64-shot row per node and the LDS accumulator [shared node][64 shots] is hit
+// by 64 consecutive words per instruction (no bank conflicts).
 template <typename T>
 using cptr = const __attribute__((address_space(4))) T*;
 
@@ -336,10 +336,26 @@ __device__ __forceinline__ cptr<T> as_const(const T* p) {
     return (cptr<T>)p;
 }
 
+// value of lane l (a wave-uniform constant) of v, as a scalar
+template <typename T>
+__device__ __forceinline__ T rlane(T v, int l);
+template <>
+__device__ __forceinline__ float rlane<float>(float v, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+template <>
+__device__ __forceinline__ double rlane<double>(double v, int l) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
+
 template <typename T, int P, int BT>
 __global__ void __launch_bounds__(BT) step_shots_kernel(const StepArgs<T> a) {
     constexpr int N = P + 1, NQ = N * N, SL = 64, NW = BT / 64;
-    constexpr int REC = 3 * NQ + 1;                    // g11[nq] g12[nq] g22[nq] c2
+    constexpr int NI = (P - 1) * (P - 1);              // element-interior nodes
+    constexpr int REC = 3 * NQ + 1 + NI;               // g11[nq] g12[nq] g22[nq] c2 dt/M[ni]
+    constexpr int NREG = (REC + 63) / 64;
     constexpr int U = 4;                               // nodes per wave per update round
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* acc = reinterpret_cast<T*>(smem_raw);            // [shared owned][64]
@@ -355,11 +371,12 @@ __global__ void __launch_bounds__(BT) step_shots_kernel(const StepArgs<T> a) {
     const int hb = a.halo_b[tile];
     const int n_items = n_own_el + (a.halo_b[tile + 1] - hb);
     const int S = a.S;
-    const cptr<int32_t> conn = as_const(a.conn);
-    const cptr<T> G = as_const(a.G);
     const cptr<int32_t> halo = as_const(a.halo);
     const cptr<T> dtminv = as_const(a.dtminv);
+    const rsrc_t r_conn = make_rsrc(a.conn, a.conn_bytes);
+    const rsrc_t r_G = make_rsrc(a.G, a.G_bytes);
     const rsrc_t r_u = make_rsrc(a.u_in, a.state_bytes);
+    const rsrc_t r_v = make_rsrc(a.v, a.state_bytes);
     const rsrc_t r_pair = make_rsrc(a.u_pair, a.u_pair ? a.state_bytes : 0u);
     const uint32_t ustride = (uint32_t)S * (uint32_t)sizeof(T);
     // this tile's point sources and receivers (per-tile lists, usually empty)
@@ -373,14 +390,53 @@ __global__ void __launch_bounds__(BT) step_shots_kernel(const StepArgs<T> a) {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const uint32_t soff = (uint32_t)(s0 + lane) * (uint32_t)sizeof(T);
+    // element k of the tile: own elements first, then the halo
+    auto elem_of = [&](int k) { return k < n_own_el ? eb + k : halo[hb + k - n_own_el]; };
+    // An element's node ids (lane q holds id q) and its record (word i in lane i % 64 of
+    // register i / 64) are read one element ahead, into VGPRs, and broadcast with readlane.
+    auto load_ids = [&](int e) {
+        return bload<int>(r_conn, (uint32_t)(e * NQ + (lane < NQ ? lane : 0)) * 4u);
+    };
+    auto load_rec = [&](int e, T* gv) {
+#pragma unroll
+        for (int rg = 0; rg < NREG; ++rg) {
+            const int w = rg * 64 + lane;
+            gv[rg] = bload<T>(r_G, (uint32_t)(e * REC + (w < REC ? w : 0)) * (uint32_t)sizeof(T));
+        }
+    };
+    int e_next = wave < n_items ? elem_of(wave) : 0;
+    int cv_next = load_ids(e_next);
+    T gv_next[NREG];
+    load_rec(e_next, gv_next);
     for (int k = wave; k < n_items; k += NW) {
         const bool own = k < n_own_el;
-        const int e = own ? eb + k : halo[hb + k - n_own_el];
-        const cptr<int32_t> ce = conn + (int64_t)e * NQ;
-        const cptr<T> ge = G + (int64_t)e * REC;
+        const int e = e_next;
+        const int cv = cv_next;
+        T gv[NREG];
+#pragma unroll
+        for (int rg = 0; rg < NREG; ++rg) gv[rg] = gv_next[rg];
         T u[NQ];
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) u[q] = bload<T>(r_u, (uint32_t)ce[q] * ustride + soff);
+        for (int q = 0; q < NQ; ++q)
+            u[q] = bload<T>(r_u, (uint32_t)__builtin_amdgcn_readlane(cv, q) * ustride + soff);
+        // v at the element-interior nodes (nodes of this element alone, finished below):
+        // requested now so that the loads overlap the contraction
+        T vin[NI > 0 ? NI : 1];
+        if (own && a.mode == 0) {
+#pragma unroll
+            for (int b = 1; b < P; ++b)
+#pragma unroll
+                for (int c = 1; c < P; ++c)
+                    vin[(b - 1) * (P - 1) + c - 1] =
+                        bload<T>(r_v, (uint32_t)__builtin_amdgcn_readlane(cv, c + N * b) * ustride + soff);
+        }
+        if (k + NW < n_items) {
+            e_next = elem_of(k + NW);
+            cv_next = load_ids(e_next);
+            load_rec(e_next, gv_next);
+        }
+        // word w of the record
+        auto rec = [&](int w) { return rlane(gv[w / 64], w % 64); };
         T r[NQ];
 #pragma unroll
         for (int q = 0; q < NQ; ++q) r[q] = T(0);
@@ -396,7 +452,7 @@ __global__ void __launch_bounds__(BT) step_shots_kernel(const StepArgs<T> a) {
                     gy += a.D[j * N + m] * u[i + N * m];
                 }
                 const int q = i + N * j;
-                const T g11 = ge[q], g12 = ge[NQ + q], g22 = ge[2 * NQ + q];
+                const T g11 = rec(q), g12 = rec(NQ + q), g22 = rec(2 * NQ + q);
                 f1[i] = g11 * gx + g12 * gy;
                 f2[i] = g12 * gx + g22 * gy;
             }
@@ -413,11 +469,12 @@ __global__ void __launch_bounds__(BT) step_shots_kernel(const StepArgs<T> a) {
                 for (int aa = 0; aa < N; ++aa) r[aa + N * bb] += a.D[j * N + bb] * f2[aa];
             }
         }
-        const T c2 = ge[3 * NQ];
+        const T c2 = rec(3 * NQ);
         if (a.grad != nullptr && own) {
             T dot = T(0);
 #pragma unroll
-            for (int q = 0; q < NQ; ++q) dot += r[q] * bload<T>(r_pair, (uint32_t)ce[q] * ustride + soff);
+            for (int q = 0; q < NQ; ++q)
+                dot += r[q] * bload<T>(r_pair, (uint32_t)__builtin_amdgcn_readlane(cv, q) * ustride + soff);
             dot = group_sum<64>(dot);
             if (lane == 0) atomicAdd(&a.grad[e], (double)dot);
         }
@@ -425,9 +482,23 @@ __global__ void __launch_bounds__(BT) step_shots_kernel(const StepArgs<T> a) {
         // elements accumulate in LDS; a node of this element alone is finished here.
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
-            const int node = ce[q];
+            const int node = __builtin_amdgcn_readlane(cv, q);
             const int loc = node - nb;
-            if ((unsigned)loc < (unsigned)ns) {
+            const int qa = q % N, qb = q / N;
+            if (qa > 0 && qa < P && qb > 0 && qb < P) {
+                // element-interior node: single-element, owned by this element's tile
+                if (own) {
+                    const T rt = c2 * r[q];
+                    const int64_t g = (int64_t)node * S + s0 + lane;
+                    if (a.mode == 0) {
+                        const T vn = vin[(qb - 1) * (P - 1) + qa - 1] - rec(3 * NQ + 1 + (qb - 1) * (P - 1) + qa - 1) * rt;
+                        a.v[g] = vn;
+                        a.u_out[g] = u[q] + a.dt * vn;
+                    } else {
+                        a.r_out[g] = a.mode == 2 ? rec(3 * NQ + 1 + (qb - 1) * (P - 1) + qa - 1) * rt : rt;
+                    }
+                }
+            } else if ((unsigned)loc < (unsigned)ns) {
                 atomicAdd(&acc[loc * SL + lane], c2 * r[q]);
             } else if (own && (unsigned)loc < (unsigned)nown) {
                 // point sources and injected residuals at such nodes are added after

@@ -135,3 +135,39 @@ def test_batch512_64_shots_apply_sampled(semlib, gpu_ok):
     r_o, _ = solver.sampled_rows(wl.vxy, wl.quads, wl.c2, wl.p, conn, nodes, x.T)
     assert rel(r[:, nodes].T, r_o) <= 3e-6
     s.close()
+
+
+def test_batch512_64_shots_step_sampled(semlib, gpu_ok):
+    """512 x 512 jittered quads, p=4, 64 shots, FP32, one leapfrog step with the 64 point
+    sources active: sampled nodes and every source node, against the oracle's rows. The
+    fields are scaled so that the source term is comparable to the stiffness term."""
+    import torch
+    say("case batch512 64-shot step")
+    wl = workloads.workload("batch512")
+    conn, n = mesh.global_numbering(wl.quads, wl.vxy.shape[0], wl.p)
+    s = semlib.Simulator(wl.vxy, wl.quads, wl.c2, wl.p, precision="f32", n_shots=64)
+    assert s.info()["shot_lanes"] == 64
+    src = s.set_sources(wl.src_xy, wl.src_shot, wl.f0)
+    x = 1e-12 * workloads.random_field(n, 64, seed=10)
+    y = 1e-12 * workloads.random_field(n, 64, seed=11)
+    s.set_field(semlib.FIELD_U, torch.tensor(x, dtype=torch.float32, device="cuda"))
+    s.set_field(semlib.FIELD_V, torch.tensor(y, dtype=torch.float32, device="cuda"))
+    s.run(1, record=False)
+    u1 = s.get_field(semlib.FIELD_U).cpu().numpy()
+    v1 = s.get_field(semlib.FIELD_V).cpu().numpy()
+    nodes = np.unique(np.concatenate([sample_nodes(n, 1500), src]))
+    r_o, M_o = solver.sampled_rows(wl.vxy, wl.quads, wl.c2, wl.p, conn, nodes, x.T)
+    f = np.zeros((nodes.size, 64))
+    amp = solver.ricker(0.0, wl.f0, 1.0 / wl.f0)
+    for k, sh in zip(src, wl.src_shot):
+        f[np.searchsorted(nodes, k), sh] += amp
+    v_o = y.T[nodes] + s.dt * (f - r_o) / M_o[:, None]
+    u_o = x.T[nodes] + s.dt * v_o
+    assert rel(v1[:, nodes].T, v_o) <= 3e-6
+    assert rel(u1[:, nodes].T, u_o) <= 3e-6
+    # the source nodes alone, where the source term is of the size of the stiffness term
+    at = np.searchsorted(nodes, src)
+    dv_src = s.dt * amp / M_o[at]
+    assert np.max(np.abs(dv_src)) > 0.5 * np.max(np.abs(v_o[at, wl.src_shot] - y.T[src, wl.src_shot]))
+    assert rel(v1[wl.src_shot, src], v_o[at, wl.src_shot]) <= 3e-6
+    s.close()

@@ -98,7 +98,7 @@ def test_64_shot_lanes_selected(semlib, gpu_ok):
     wl = workloads.workload("batch512", n=16, n_shots=64)
     s = semlib.Simulator(wl.vxy, wl.quads, wl.c2, wl.p, precision="f32", n_shots=64)
     inf = s.info()
-    assert inf["shot_lanes"] == 64 and inf["block_threads"] == 1024
+    assert inf["shot_lanes"] == 64 and inf["block_threads"] == 256
     assert inf["max_accum_nodes"] * 64 * 4 <= 32 * 1024 < inf["max_owned_nodes"] * 64 * 4
     s.close()
 
