@@ -936,6 +936,96 @@ const char* sem_last_error(const sem_ctx* c) {
     return c->err.c_str();
 }
 
+int sem_autotune(const sem_mesh* mesh, const sem_options* base, int32_t warmup, int32_t steps,
+                 sem_options* best, double* best_us, double* table, int32_t table_cap, int32_t* n_tried) {
+    if (!mesh || !base || !best || !best_us || steps < 1 || warmup < 0 || table_cap < 0) {
+        g_create_error = "sem_autotune: bad arguments";
+        return SEM_ERR_INVALID_ARG;
+    }
+    if (base->device < 0) {
+        g_create_error = "sem_autotune needs a device";
+        return SEM_ERR_NO_DEVICE;
+    }
+    std::vector<sem_options> cand;
+    auto vary_threads = [&](const std::vector<int>& bts, sem_options o) {
+        if (o.block_threads > 0) { cand.push_back(o); return; }
+        for (int bt : bts) { o.block_threads = bt; cand.push_back(o); }
+    };
+    const int S = base->n_shots;
+    if (S == 1) {
+        vary_threads({256, 512, 1024}, *base);
+    } else if (S % 64 == 0 && (base->shot_lanes == 0 || base->shot_lanes == 64)) {
+        sem_options o = *base;
+        if (o.lds_bytes > 0) {
+            vary_threads({256, 512}, o);
+        } else {
+            for (int kb : {24, 32, 48, 64}) { o.lds_bytes = kb * 1024; vary_threads({256, 512}, o); }
+        }
+    } else {
+        sem_options o = *base;
+        if (o.shot_lanes > 0) {
+            cand.push_back(o);
+        } else {
+            for (int sl = 1; sl <= 16; sl *= 2)
+                if (S % sl == 0) { o.shot_lanes = sl; cand.push_back(o); }
+        }
+    }
+    if (hipSetDevice(base->device) != hipSuccess) {
+        g_create_error = "sem_autotune: hipSetDevice failed";
+        return SEM_ERR_HIP;
+    }
+    hipStream_t st = (hipStream_t)base->stream;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (hipEventCreate(&ev0) != hipSuccess || hipEventCreate(&ev1) != hipSuccess) {
+        if (ev0) (void)hipEventDestroy(ev0);
+        g_create_error = "sem_autotune: hipEventCreate failed";
+        return SEM_ERR_HIP;
+    }
+    int found = -1, last_rc = SEM_OK;
+    std::string last_err;
+    double best_t = 0.0;
+    for (size_t k = 0; k < cand.size(); ++k) {
+        double us = -1.0;
+        sem_ctx* c = nullptr;
+        int rc = sem_create(mesh, &cand[k], &c);
+        if (rc == SEM_OK) {
+            rc = sem_run(c, warmup, nullptr);
+            if (rc == SEM_OK && hipEventRecord(ev0, st) != hipSuccess) rc = SEM_ERR_HIP;
+            if (rc == SEM_OK) rc = sem_run(c, steps, nullptr);
+            if (rc == SEM_OK && hipEventRecord(ev1, st) != hipSuccess) rc = SEM_ERR_HIP;
+            if (rc == SEM_OK && hipEventSynchronize(ev1) != hipSuccess) rc = SEM_ERR_HIP;
+            float ms = 0.0f;
+            if (rc == SEM_OK && hipEventElapsedTime(&ms, ev0, ev1) != hipSuccess) rc = SEM_ERR_HIP;
+            if (rc == SEM_OK) us = 1e3 * (double)ms / steps;
+            else last_err = sem_last_error(c);
+            sem_destroy(c);
+        } else {
+            last_err = g_create_error;
+        }
+        if (rc != SEM_OK) last_rc = rc;
+        if (us > 0.0 && (found < 0 || us < best_t)) {
+            found = (int)k;
+            best_t = us;
+        }
+        if (table && (int32_t)k < table_cap) {
+            table[4 * k + 0] = cand[k].block_threads;
+            table[4 * k + 1] = cand[k].shot_lanes;
+            table[4 * k + 2] = cand[k].lds_bytes;
+            table[4 * k + 3] = us;
+        }
+    }
+    (void)hipEventDestroy(ev0);
+    (void)hipEventDestroy(ev1);
+    if (n_tried) *n_tried = (int32_t)cand.size();
+    if (found < 0) {
+        g_create_error = "sem_autotune: no candidate could run: " + last_err;
+        return last_rc != SEM_OK ? last_rc : SEM_ERR_INVALID_ARG;
+    }
+    *best = cand[found];
+    *best_us = best_t;
+    return SEM_OK;
+}
+
 void sem_destroy(sem_ctx* c) {
     if (!c) return;
     if (!c->host_only) {

@@ -63,7 +63,7 @@ EXPORTS = ("sem_create", "sem_create_error", "sem_get_info", "sem_get_permutatio
            "sem_get_node_coords", "sem_set_sources", "sem_set_receivers", "sem_set_c2", "sem_reset",
            "sem_run", "sem_step", "sem_get_field", "sem_set_field", "sem_apply_stiffness",
            "sem_adjoint_gradient", "sem_synchronize", "sem_hilbert_index", "sem_last_error",
-           "sem_destroy")
+           "sem_destroy", "sem_autotune")
 
 
 def _load():
@@ -99,6 +99,9 @@ def _load():
     lib.sem_last_error.restype = ctypes.c_char_p
     lib.sem_destroy.argtypes = [P]
     lib.sem_destroy.restype = None
+    lib.sem_autotune.argtypes = [ctypes.POINTER(_Mesh), ctypes.POINTER(_Options), I32, I32,
+                                 ctypes.POINTER(_Options), ctypes.POINTER(D), VP, I32,
+                                 ctypes.POINTER(I32)]
     return lib
 
 
@@ -308,6 +311,42 @@ def _make_forward():
 
 
 _SemForward = None
+
+
+def autotune(vxy, quads, c2, p: int, precision: str = "f32", order: str = "hilbert", n_shots: int = 1,
+             device: int = 0, warmup: int = 3, steps: int = 20, stream=None, **fixed):
+    """Time the step kernel over the library's candidate launch configurations (see
+    sem_autotune) and return (best, table): ``best`` holds the Simulator keyword arguments
+    of the fastest (block_threads, shot_lanes, lds_bytes, us_per_step); ``table`` one dict
+    per candidate. Keyword arguments in ``fixed`` (block_threads, shot_lanes, lds_bytes,
+    tile_items, tile_elems, dt, cfl, seed) are held fixed."""
+    import torch
+    vxy = np.ascontiguousarray(vxy, dtype=np.float64)
+    quads = np.ascontiguousarray(quads, dtype=np.int32)
+    c2 = np.ascontiguousarray(c2, dtype=np.float64)
+    if stream is None:
+        with torch.cuda.device(device):
+            stream = torch.cuda.current_stream(device).cuda_stream
+    m = _Mesh(vxy.shape[0], _ptr(vxy), quads.shape[0], _ptr(quads), _ptr(c2))
+    f = dict(fixed)
+    o = _Options(p, F64 if precision == "f64" else F32, ORDERS[order], NODE_ORDERS["first_touch"],
+                 f.pop("seed", 3), n_shots, device, f.pop("dt", 0.0), f.pop("cfl", 0.3), stream or 0,
+                 f.pop("tile_elems", 0), f.pop("shot_lanes", 0), f.pop("tile_items", 0),
+                 f.pop("block_threads", 0), f.pop("lds_bytes", 0))
+    if f:
+        raise TypeError(f"unknown fixed options {sorted(f)}")
+    best = _Options()
+    best_us = ctypes.c_double()
+    table = np.zeros((64, 4), np.float64)
+    n = ctypes.c_int32()
+    rc = _lib.sem_autotune(ctypes.byref(m), ctypes.byref(o), warmup, steps, ctypes.byref(best),
+                           ctypes.byref(best_us), _ptr(table), table.shape[0], ctypes.byref(n))
+    if rc:
+        raise SemError(rc, _lib.sem_create_error().decode())
+    rows = [dict(block_threads=int(r[0]), shot_lanes=int(r[1]), lds_bytes=int(r[2]), us_per_step=float(r[3]))
+            for r in table[:min(n.value, table.shape[0])]]
+    return (dict(block_threads=best.block_threads, shot_lanes=best.shot_lanes, lds_bytes=best.lds_bytes,
+                 us_per_step=best_us.value), rows)
 
 
 def sem_forward(c2, sim: Simulator, nsteps: int, ckpt_every: int = 40):

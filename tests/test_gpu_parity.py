@@ -259,3 +259,26 @@ def test_unstable_dt_rejected(semlib, gpu_ok):
     with pytest.raises(semlib.SemError) as ei:
         semlib.Simulator(wl.vxy, wl.quads, wl.c2, wl.p, precision="f64", dt=1.5 * inf["dt_stable"])
     assert ei.value.status == "UNSTABLE_DT"
+
+
+@pytest.mark.parametrize("shots", [1, 64])
+def test_autotune_picks_a_timed_candidate(semlib, gpu_ok, shots):
+    """The autotuner times every candidate, returns the fastest, and a context built with
+    its options reproduces the default context's wavefield to rounding."""
+    import torch
+    say("case autotune", shots)
+    wl = workloads.workload("batch512", n=32, n_shots=shots, nsteps=60)
+    best, rows = semlib.autotune(wl.vxy, wl.quads, wl.c2, wl.p, precision="f32", n_shots=shots, steps=10)
+    assert len(rows) == (3 if shots == 1 else 8)
+    assert all(r["us_per_step"] > 0 for r in rows)
+    assert best["us_per_step"] == min(r["us_per_step"] for r in rows)
+    kw = {k: best[k] for k in ("block_threads", "lds_bytes")}
+    out = []
+    for opts in (kw, {}):
+        s = semlib.Simulator(wl.vxy, wl.quads, wl.c2, wl.p, precision="f32", n_shots=shots, **opts)
+        s.set_sources(wl.src_xy, wl.src_shot, wl.f0)
+        s.run(wl.nsteps, record=False)
+        out.append(s.get_field(semlib.FIELD_U).double().cpu().numpy())
+        s.close()
+    assert np.abs(out[0]).max() > 0
+    assert rel(out[0], out[1]) <= 1e-5

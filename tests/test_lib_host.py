@@ -165,3 +165,10 @@ def test_error_paths(semlib):
     assert _err(semlib, lambda: s.set_sources([[0.5, 0.5]], [0], -1.0)) == "INVALID_ARG"
     with pytest.raises(semlib.SemError):
         semlib.hilbert_index(4, 4, [4], [0])
+
+
+def test_autotune_needs_device(semlib):
+    wl = workloads.workload("homog64", n=8)
+    with pytest.raises(semlib.SemError) as ei:
+        semlib.autotune(wl.vxy, wl.quads, wl.c2, wl.p, device=-1, stream=0)
+    assert ei.value.status == "NO_DEVICE"
