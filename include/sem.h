@@ -83,7 +83,8 @@ typedef struct {
     int32_t block_threads;   /* workgroup size 256/512/1024 of the single-shot and the  *
                               * 64-shot kernels; 0 = automatic                          */
     int32_t lds_bytes;       /* LDS budget of a tile's owned-node accumulator, bytes,    *
-                              * <= 163840; 0 = automatic                                */
+                              * <= 163840 (the 64-shot kernel accumulates in FP64 in    *
+                              * either precision); 0 = automatic                        */
 } sem_options;
 
 typedef struct {

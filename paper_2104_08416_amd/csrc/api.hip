@@ -140,11 +140,11 @@ sem::StepArgs<T> base_args(sem_ctx* c) {
     return a;
 }
 
-// accumulator bytes of the largest tile: all owned nodes, or (64-shot kernel) the owned
-// nodes of two or more elements
+// accumulator bytes of the largest tile: all owned nodes, or (64-shot kernel, FP64
+// accumulators in either precision) the owned nodes of two or more elements
 size_t lds_bytes(const sem_ctx* c) {
-    const int32_t slots = c->geo >= sem::kGeoShots ? c->plan.max_shared : c->plan.max_owned;
-    return (size_t)slots * c->SL * c->wsize;
+    if (c->geo >= sem::kGeoShots) return (size_t)c->plan.max_shared * c->SL * sizeof(double);
+    return (size_t)c->plan.max_owned * c->SL * c->wsize;
 }
 
 template <typename T>
@@ -358,12 +358,12 @@ int pick_tile_items(int p, int sl, int row_block, int requested) {
 }
 
 // Accumulator slots per tile: the LDS accumulator [slots][shot_lanes] fills lds_budget
-// bytes (default 64 KB; 64-shot kernel 32 KB in FP32 and 48 KB in FP64, measured on the
-// 512^2 p=4 batch: several workgroups per CU beat larger tiles with fewer halo elements).
+// bytes (default 64 KB; 64-shot kernel, whose accumulators are FP64: 64 KB with 512
+// threads in FP32, 48 KB with 256 threads in FP64, measured on the 512^2 p=4 batch).
 int pick_max_owned(int sl, int precision, int lds_budget) {
-    const int word = precision == SEM_F64 ? 8 : 4;
+    const int word = (precision == SEM_F64 || sl == 64) ? 8 : 4;
     int budget = lds_budget;
-    if (budget <= 0) budget = sl == 64 ? (precision == SEM_F64 ? 48 : 32) * 1024 : 65536;
+    if (budget <= 0) budget = sl == 64 ? (precision == SEM_F64 ? 48 : 64) * 1024 : 65536;
     return budget / (sl * word);
 }
 
@@ -687,9 +687,10 @@ int sem_create(const sem_mesh* mesh, const sem_options* opt, sem_ctx** out) {
     }
     // single shot: row kernel with in-kernel geometry; 64-shot lanes: one wave per element
     if (c->S == 1) c->geo = row_block * 8 + np;
-    // 64 shots: 256 threads (p = 4: about 100 VGPRs in FP32, 170 in FP64, no spills)
+    // 64 shots: FP32 512 threads, FP64 256 (p = 4: about 100 VGPRs in FP32, 170 in FP64)
     else if (c->SL == 64)
-        c->geo = sem::kGeoShots + (opt->block_threads > 0 ? row_block : 256);
+        c->geo = sem::kGeoShots +
+                 (opt->block_threads > 0 ? row_block : (opt->precision == SEM_F64 ? 256 : 512));
     else c->geo = 0;
     int code = SEM_OK;
     std::string err;

@@ -69,6 +69,16 @@ __device__ __forceinline__ int bload<int>(rsrc_t r, uint32_t off) {
     return (int)__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
 }
 
+// Raw buffer stores (vector memory), same 32-bit offsets; stores past the descriptor's
+// byte count are dropped.
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void bstore(rsrc_t r, uint32_t off, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, off, 0, 0);
+}
+__device__ __forceinline__ void bstore(rsrc_t r, uint32_t off, double v) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
+}
+
 // N consecutive dwords with the widest loads available (16, 8, then 4 bytes)
 template <int N>
 __device__ __forceinline__ void load_ids(rsrc_t r, uint32_t off, int (&out)[N]) {
@@ -358,7 +368,10 @@ __global__ void __launch_bounds__(BT) step_shots_kernel(const StepArgs<T> a) {
     constexpr int NREG = (REC + 63) / 64;
     constexpr int U = 4;                               // nodes per wave per update round
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    T* acc = reinterpret_cast<T*>(smem_raw);            // [shared owned][64]
+    // [shared owned][64] in FP64 for either precision: ds_add_f64 sustains a much higher
+    // rate than ds_add_f32 here (the FP32 step ran 1.3x faster with FP64 accumulators),
+    // and the sum rounds once
+    double* acc = reinterpret_cast<double*>(smem_raw);
 
     const int logical = xcd_logical_block();
     const int tile = logical / a.n_slices;
@@ -377,6 +390,8 @@ __global__ void __launch_bounds__(BT) step_shots_kernel(const StepArgs<T> a) {
     const rsrc_t r_G = make_rsrc(a.G, a.G_bytes);
     const rsrc_t r_u = make_rsrc(a.u_in, a.state_bytes);
     const rsrc_t r_v = make_rsrc(a.v, a.state_bytes);
+    const rsrc_t r_uo = make_rsrc(a.u_out, a.u_out ? a.state_bytes : 0u);
+    const rsrc_t r_ro = make_rsrc(a.r_out, a.r_out ? a.state_bytes : 0u);
     const rsrc_t r_pair = make_rsrc(a.u_pair, a.u_pair ? a.state_bytes : 0u);
     const uint32_t ustride = (uint32_t)S * (uint32_t)sizeof(T);
     // this tile's point sources and receivers (per-tile lists, usually empty)
@@ -384,7 +399,7 @@ __global__ void __launch_bounds__(BT) step_shots_kernel(const StepArgs<T> a) {
     const int rb = a.rec_b ? a.rec_b[tile] : 0, re = a.rec_b ? a.rec_b[tile + 1] : 0;
     const T amp = se > sb ? (T)ricker(a.src_t, a.f0, a.t0) : T(0);
 
-    for (int i = threadIdx.x; i < ns * SL; i += BT) acc[i] = T(0);
+    for (int i = threadIdx.x; i < ns * SL; i += BT) acc[i] = 0.0;
     __syncthreads();
 
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -482,36 +497,48 @@ __global__ void __launch_bounds__(BT) step_shots_kernel(const StepArgs<T> a) {
         // elements accumulate in LDS; a node of this element alone is finished here.
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
+            const int qa = q % N, qb = q / N;
+            if (qa > 0 && qa < P && qb > 0 && qb < P) continue;     // interior: below
             const int node = __builtin_amdgcn_readlane(cv, q);
             const int loc = node - nb;
-            const int qa = q % N, qb = q / N;
-            if (qa > 0 && qa < P && qb > 0 && qb < P) {
-                // element-interior node: single-element, owned by this element's tile
-                if (own) {
-                    const T rt = c2 * r[q];
-                    const int64_t g = (int64_t)node * S + s0 + lane;
-                    if (a.mode == 0) {
-                        const T vn = vin[(qb - 1) * (P - 1) + qa - 1] - rec(3 * NQ + 1 + (qb - 1) * (P - 1) + qa - 1) * rt;
-                        a.v[g] = vn;
-                        a.u_out[g] = u[q] + a.dt * vn;
-                    } else {
-                        a.r_out[g] = a.mode == 2 ? rec(3 * NQ + 1 + (qb - 1) * (P - 1) + qa - 1) * rt : rt;
-                    }
-                }
-            } else if ((unsigned)loc < (unsigned)ns) {
-                atomicAdd(&acc[loc * SL + lane], c2 * r[q]);
+            if ((unsigned)loc < (unsigned)ns) {
+                atomicAdd(&acc[loc * SL + lane], (double)(c2 * r[q]));
             } else if (own && (unsigned)loc < (unsigned)nown) {
-                // point sources and injected residuals at such nodes are added after
-                // the element loop, as corrections of v and u
+                // a node on the domain boundary that only this element touches
                 const T rt = c2 * r[q];
-                const int64_t g = (int64_t)node * S + s0 + lane;
+                const uint32_t off = (uint32_t)node * ustride + soff;
                 if (a.mode == 0) {
-                    const T vn = a.v[g] - dtminv[node] * rt;
-                    a.v[g] = vn;
-                    a.u_out[g] = u[q] + a.dt * vn;
+                    const T vn = bload<T>(r_v, off) - dtminv[node] * rt;
+                    bstore(r_v, off, vn);
+                    bstore(r_uo, off, u[q] + a.dt * vn);
                 } else {
-                    a.r_out[g] = a.mode == 2 ? dtminv[node] * rt : rt;
+                    bstore(r_ro, off, a.mode == 2 ? dtminv[node] * rt : rt);
                 }
+            }
+        }
+        // element-interior nodes: single-element, owned by this element's tile
+        if (own) {
+            if (a.mode == 0) {
+#pragma unroll
+                for (int b = 1; b < P; ++b)
+#pragma unroll
+                    for (int c = 1; c < P; ++c) {
+                        const int q = c + N * b, ii = (b - 1) * (P - 1) + c - 1;
+                        const uint32_t off = (uint32_t)__builtin_amdgcn_readlane(cv, q) * ustride + soff;
+                        const T vn = vin[ii] - rec(3 * NQ + 1 + ii) * (c2 * r[q]);
+                        bstore(r_v, off, vn);
+                        bstore(r_uo, off, u[q] + a.dt * vn);
+                    }
+            } else {
+#pragma unroll
+                for (int b = 1; b < P; ++b)
+#pragma unroll
+                    for (int c = 1; c < P; ++c) {
+                        const int q = c + N * b, ii = (b - 1) * (P - 1) + c - 1;
+                        const uint32_t off = (uint32_t)__builtin_amdgcn_readlane(cv, q) * ustride + soff;
+                        const T rt = c2 * r[q];
+                        bstore(r_ro, off, a.mode == 2 ? rec(3 * NQ + 1 + ii) * rt : rt);
+                    }
             }
         }
     }
@@ -526,7 +553,7 @@ __global__ void __launch_bounds__(BT) step_shots_kernel(const StepArgs<T> a) {
             if ((unsigned)sh >= (unsigned)SL) continue;
             const T f = a.src_w[i] * amp;
             if (loc < ns) {
-                atomicAdd(&acc[loc * SL + sh], -f);
+                atomicAdd(&acc[loc * SL + sh], -(double)f);
             } else {
                 const int64_t g = (int64_t)(nb + loc) * S + s0 + sh;
                 const T dv = a.dtminv[nb + loc] * f;
@@ -542,7 +569,7 @@ __global__ void __launch_bounds__(BT) step_shots_kernel(const StepArgs<T> a) {
             const T f = a.inj[((int64_t)(s0 + sh) * a.n_rec + a.rec_idx[kk]) * a.inj_cols + a.inj_col] *
                         a.inj_scale;
             if (loc < ns) {
-                atomicAdd(&acc[loc * SL + sh], -f);
+                atomicAdd(&acc[loc * SL + sh], -(double)f);
             } else {
                 const int64_t g = (int64_t)(nb + loc) * S + s0 + sh;
                 const T dv = a.dtminv[nb + loc] * f;
@@ -554,9 +581,8 @@ __global__ void __launch_bounds__(BT) step_shots_kernel(const StepArgs<T> a) {
     }
     if (a.mode == 0) {
         // one wave per accumulated node, U nodes per round with all loads issued first
-        const rsrc_t r_v = make_rsrc(a.v, a.state_bytes);
         for (int l0 = wave; l0 < ns; l0 += NW * U) {
-            T vv[U], uu[U], mm[U], ac[U];
+            T vv[U], uu[U], mm[U], ac[U];           // ac: the accumulated K u - f, rounded
 #pragma unroll
             for (int t = 0; t < U; ++t) {
                 const int loc = l0 + t * NW;
@@ -564,18 +590,18 @@ __global__ void __launch_bounds__(BT) step_shots_kernel(const StepArgs<T> a) {
                 vv[t] = bload<T>(r_v, off);
                 uu[t] = bload<T>(r_u, off);
                 mm[t] = loc < ns ? dtminv[nb + loc] : T(0);
-                ac[t] = loc < ns ? acc[loc * SL + lane] : T(0);
+                ac[t] = loc < ns ? (T)acc[loc * SL + lane] : T(0);
             }
 #pragma unroll
             for (int t = 0; t < U; ++t) {
                 const int loc = l0 + t * NW;
                 if (loc < ns) {
-                    const int64_t g = (int64_t)(nb + loc) * S + s0 + lane;
+                    const uint32_t off = (uint32_t)(nb + loc) * ustride + soff;
                     const T vn = vv[t] - mm[t] * ac[t];
-                    a.v[g] = vn;
+                    bstore(r_v, off, vn);
                     const T un = uu[t] + a.dt * vn;
-                    a.u_out[g] = un;
-                    acc[loc * SL + lane] = un;
+                    bstore(r_uo, off, un);
+                    acc[loc * SL + lane] = (double)un;
                 }
             }
         }
@@ -585,16 +611,15 @@ __global__ void __launch_bounds__(BT) step_shots_kernel(const StepArgs<T> a) {
                 const int kk = rb + i / SL, sh = i % SL, loc = a.rec_loc[kk];
                 // single-element nodes: read back from L2 (the corrections above are atomics)
                 a.trace[((int64_t)(s0 + sh) * a.n_rec + a.rec_idx[kk]) * a.trace_cols + a.trace_col] =
-                    loc < ns ? acc[loc * SL + sh]
+                    loc < ns ? (T)acc[loc * SL + sh]
                              : __hip_atomic_load(&a.u_out[(int64_t)(nb + loc) * S + s0 + sh], __ATOMIC_RELAXED,
                                                  __HIP_MEMORY_SCOPE_AGENT);
             }
         }
     } else {
-        for (int loc = wave; loc < ns; loc += NW) {
-            const int64_t g = (int64_t)(nb + loc) * S + s0 + lane;
-            a.r_out[g] = a.mode == 2 ? dtminv[nb + loc] * acc[loc * SL + lane] : acc[loc * SL + lane];
-        }
+        for (int loc = wave; loc < ns; loc += NW)
+            bstore(r_ro, (uint32_t)(nb + loc) * ustride + soff,
+                   a.mode == 2 ? dtminv[nb + loc] * (T)acc[loc * SL + lane] : (T)acc[loc * SL + lane]);
     }
 }
 
@@ -624,9 +649,11 @@ step_rows_kernel(const StepArgs<T> a) {
     constexpr int EPB = EPW * (kRowBlock / 64);        // elements per workgroup pass
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* stage = reinterpret_cast<T*>(smem_raw);          // [EPB][NQP]
-    T* acc = stage + EPB * NQP;                         // [owned nodes]
+    // [owned nodes] in FP64 for either precision (ds_add_f64 sustains a higher rate than
+    // ds_add_f32 on this chip, and the sum rounds once)
+    double* acc = reinterpret_cast<double*>(stage + EPB * NQP);
     // owned v, u_in and dt/M prefetched for the update phase: [3][a.lds_own] (64-aligned)
-    T* pre_v = acc + a.lds_own;
+    T* pre_v = reinterpret_cast<T*>(acc + a.lds_own);
     T* pre_u = pre_v + a.lds_own;
     T* pre_m = pre_u + a.lds_own;
 
@@ -652,7 +679,7 @@ step_rows_kernel(const StepArgs<T> a) {
         lds_prefetch<RB>(r_u, off, pre_u, ndw);
         lds_prefetch<RB>(make_rsrc(a.dtminv, a.state_bytes), off, pre_m, ndw);
     }
-    for (int i = threadIdx.x; i < nown; i += kRowBlock) acc[i] = T(0);
+    for (int i = threadIdx.x; i < nown; i += kRowBlock) acc[i] = 0.0;
     __syncthreads();
 
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -776,8 +803,8 @@ step_rows_kernel(const StepArgs<T> a) {
             for (int aa = 0; aa < N; ++aa) {
                 const int loc = idx[pp][aa] - nb;
                 if ((unsigned)loc < (unsigned)nown) {
-                    if (aa > 0 && aa < P && inner_row) acc[loc] = bl[pp][6] * r[aa];
-                    else atomicAdd(&acc[loc], bl[pp][6] * r[aa]);
+                    if (aa > 0 && aa < P && inner_row) acc[loc] = (double)(bl[pp][6] * r[aa]);
+                    else atomicAdd(&acc[loc], (double)(bl[pp][6] * r[aa]));
                 }
             }
         }
@@ -790,7 +817,7 @@ step_rows_kernel(const StepArgs<T> a) {
         if (se > sb) {
             const T amp = (T)ricker(a.src_t, a.f0, a.t0);
             for (int i = sb + threadIdx.x; i < se; i += kRowBlock)
-                if (a.src_shot[i] == 0) atomicAdd(&acc[a.src_loc[i]], -a.src_w[i] * amp);
+                if (a.src_shot[i] == 0) atomicAdd(&acc[a.src_loc[i]], -(double)(a.src_w[i] * amp));
             __syncthreads();
         }
     }
@@ -799,7 +826,7 @@ step_rows_kernel(const StepArgs<T> a) {
         if (re > rb) {
             for (int i = rb + threadIdx.x; i < re; i += kRowBlock) {
                 const T val = a.inj[(int64_t)a.rec_idx[i] * a.inj_cols + a.inj_col];
-                atomicAdd(&acc[a.rec_loc[i]], -val * a.inj_scale);
+                atomicAdd(&acc[a.rec_loc[i]], -(double)(val * a.inj_scale));
             }
             __syncthreads();
         }
@@ -807,23 +834,23 @@ step_rows_kernel(const StepArgs<T> a) {
     if (a.mode == 0) {
         // owned-node update from the prefetched operands
         for (int i = threadIdx.x; i < nown; i += kRowBlock) {
-            const T vn = pre_v[i] - pre_m[i] * acc[i];
+            const T vn = pre_v[i] - pre_m[i] * (T)acc[i];
             const T un = pre_u[i] + a.dt * vn;
             a.v[nb + i] = vn;
             a.u_out[nb + i] = un;
-            acc[i] = un;
+            acc[i] = (double)un;
         }
         if (a.trace != nullptr) {
             const int rb = a.rec_b[tile], re = a.rec_b[tile + 1];
             if (re > rb) {
                 __syncthreads();
                 for (int i = rb + threadIdx.x; i < re; i += kRowBlock)
-                    a.trace[(int64_t)a.rec_idx[i] * a.trace_cols + a.trace_col] = acc[a.rec_loc[i]];
+                    a.trace[(int64_t)a.rec_idx[i] * a.trace_cols + a.trace_col] = (T)acc[a.rec_loc[i]];
             }
         }
     } else {
         for (int i = threadIdx.x; i < nown; i += kRowBlock)
-            a.r_out[nb + i] = a.mode == 2 ? a.dtminv[nb + i] * acc[i] : acc[i];
+            a.r_out[nb + i] = a.mode == 2 ? a.dtminv[nb + i] * (T)acc[i] : (T)acc[i];
     }
 }
 
@@ -845,7 +872,7 @@ hipError_t launch_rows(int64_t n_tiles, size_t lds, const StepArgs<T>& a, hipStr
     auto fn = step_rows_kernel<T, P, RB, NP>;
     constexpr int N = P + 1, NQP = (N * N + 3) & ~3, EPB = (64 / N) * (RB / 64);
     // stage + accumulator + three prefetch arrays of a.lds_own entries each
-    lds = (size_t)EPB * NQP * sizeof(T) + (size_t)4 * a.lds_own * sizeof(T);
+    lds = (size_t)EPB * NQP * sizeof(T) + (size_t)a.lds_own * sizeof(double) + (size_t)3 * a.lds_own * sizeof(T);
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

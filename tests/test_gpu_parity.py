@@ -98,8 +98,8 @@ def test_64_shot_lanes_selected(semlib, gpu_ok):
     wl = workloads.workload("batch512", n=16, n_shots=64)
     s = semlib.Simulator(wl.vxy, wl.quads, wl.c2, wl.p, precision="f32", n_shots=64)
     inf = s.info()
-    assert inf["shot_lanes"] == 64 and inf["block_threads"] == 256
-    assert inf["max_accum_nodes"] * 64 * 4 <= 32 * 1024 < inf["max_owned_nodes"] * 64 * 4
+    assert inf["shot_lanes"] == 64 and inf["block_threads"] == 512
+    assert inf["max_accum_nodes"] * 64 * 8 <= 64 * 1024 < inf["max_owned_nodes"] * 64 * 8
     s.close()
 
 

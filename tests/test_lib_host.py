@@ -60,7 +60,7 @@ def test_64_shot_lanes_regroup_owned_nodes(semlib, name, kw):
     s = semlib.Simulator(wl.vxy, wl.quads, wl.c2, wl.p, device=-1, n_shots=64, lds_bytes=16384)
     inf = s.info()
     assert inf["shot_lanes"] == 64
-    assert 0 < inf["max_accum_nodes"] <= 16384 // (64 * 4) < inf["max_owned_nodes"]
+    assert 0 < inf["max_accum_nodes"] <= 16384 // (64 * 8) < inf["max_owned_nodes"]
     e, n = s.permutations()
     s.close()
     np.testing.assert_array_equal(e, oe)
