@@ -144,7 +144,7 @@ sem::StepArgs<T> base_args(sem_ctx* c) {
 // accumulators in either precision) the owned nodes of two or more elements
 size_t lds_bytes(const sem_ctx* c) {
     if (c->geo >= sem::kGeoShots) return (size_t)c->plan.max_shared * c->SL * sizeof(double);
-    return (size_t)c->plan.max_owned * c->SL * c->wsize;
+    return (size_t)c->plan.max_owned * c->SL * sizeof(double);
 }
 
 template <typename T>
@@ -361,7 +361,8 @@ int pick_tile_items(int p, int sl, int row_block, int requested) {
 // bytes (default 64 KB; 64-shot kernel, whose accumulators are FP64: 64 KB with 512
 // threads in FP32, 48 KB with 256 threads in FP64, measured on the 512^2 p=4 batch).
 int pick_max_owned(int sl, int precision, int lds_budget) {
-    const int word = (precision == SEM_F64 || sl == 64) ? 8 : 4;
+    (void)precision;
+    const int word = 8;                           // accumulators are FP64 in every kernel
     int budget = lds_budget;
     if (budget <= 0) budget = sl == 64 ? (precision == SEM_F64 ? 48 : 64) * 1024 : 65536;
     return budget / (sl * word);

@@ -151,7 +151,7 @@ template <typename T, int P, int SL, int GEO>
 __global__ void __launch_bounds__(kBlock, sizeof(T) == 8 ? SEM_MIN_WAVES_F64 : SEM_MIN_WAVES_F32) step_kernel(const StepArgs<T> a) {
     constexpr int N = P + 1, NQ = N * N;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    T* acc = reinterpret_cast<T*>(smem_raw);
+    double* acc = reinterpret_cast<double*>(smem_raw);   // FP64 in either precision
 
     const int logical = xcd_logical_block();
     const int tile = logical / a.n_slices;
@@ -171,7 +171,7 @@ __global__ void __launch_bounds__(kBlock, sizeof(T) == 8 ? SEM_MIN_WAVES_F64 : S
     const rsrc_t r_pair = make_rsrc(a.u_pair, a.u_pair ? a.state_bytes : 0u);
     const uint32_t ustride = (uint32_t)S * (uint32_t)sizeof(T);
 
-    for (int i = threadIdx.x; i < nown * SL; i += kBlock) acc[i] = T(0);
+    for (int i = threadIdx.x; i < nown * SL; i += kBlock) acc[i] = 0.0;
     __syncthreads();
 
     const int n_items = (n_own_el + n_halo) * SL;
@@ -263,8 +263,8 @@ __global__ void __launch_bounds__(kBlock, sizeof(T) == 8 ? SEM_MIN_WAVES_F64 : S
             const int loc = node - nb;
             const int qa = q % N, qb = q / N;
             if ((unsigned)loc < (unsigned)nown) {
-                if (qa > 0 && qa < P && qb > 0 && qb < P) acc[loc * SL + s] = c2 * r[q];
-                else atomicAdd(&acc[loc * SL + s], c2 * r[q]);
+                if (qa > 0 && qa < P && qb > 0 && qb < P) acc[loc * SL + s] = (double)(c2 * r[q]);
+                else atomicAdd(&acc[loc * SL + s], (double)(c2 * r[q]));
             }
         }
         if (a.grad != nullptr) {
@@ -282,7 +282,7 @@ __global__ void __launch_bounds__(kBlock, sizeof(T) == 8 ? SEM_MIN_WAVES_F64 : S
             const T amp = (T)ricker(a.src_t, a.f0, a.t0);
             for (int i = sb + threadIdx.x; i < se; i += kBlock) {
                 const int sh = a.src_shot[i] - s0;
-                if ((unsigned)sh < (unsigned)SL) atomicAdd(&acc[a.src_loc[i] * SL + sh], -a.src_w[i] * amp);
+                if ((unsigned)sh < (unsigned)SL) atomicAdd(&acc[a.src_loc[i] * SL + sh], -(double)(a.src_w[i] * amp));
             }
             __syncthreads();
         }
@@ -294,7 +294,7 @@ __global__ void __launch_bounds__(kBlock, sizeof(T) == 8 ? SEM_MIN_WAVES_F64 : S
             for (int i = threadIdx.x; i < (re - rb) * SL; i += kBlock) {
                 const int k = rb + i / SL, s = i % SL;
                 const T val = a.inj[((int64_t)(s0 + s) * a.n_rec + a.rec_idx[k]) * a.inj_cols + a.inj_col];
-                atomicAdd(&acc[a.rec_loc[k] * SL + s], -val * a.inj_scale);
+                atomicAdd(&acc[a.rec_loc[k] * SL + s], -(double)(val * a.inj_scale));
             }
             __syncthreads();
         }
@@ -305,11 +305,11 @@ __global__ void __launch_bounds__(kBlock, sizeof(T) == 8 ? SEM_MIN_WAVES_F64 : S
             const int loc = i / SL, s = i - (i / SL) * SL;
             const int node = nb + loc;
             const int64_t g = (int64_t)node * S + s0 + s;
-            const T vn = a.v[g] - a.dtminv[node] * acc[i];
+            const T vn = a.v[g] - a.dtminv[node] * (T)acc[i];
             a.v[g] = vn;
             const T un = a.u_in[g] + a.dt * vn;
             a.u_out[g] = un;
-            acc[i] = un;
+            acc[i] = (double)un;
         }
         if (a.trace != nullptr) {
             const int rb = a.rec_b[tile], re = a.rec_b[tile + 1];
@@ -318,7 +318,7 @@ __global__ void __launch_bounds__(kBlock, sizeof(T) == 8 ? SEM_MIN_WAVES_F64 : S
                 for (int i = threadIdx.x; i < (re - rb) * SL; i += kBlock) {
                     const int k = rb + i / SL, s = i % SL;
                     a.trace[((int64_t)(s0 + s) * a.n_rec + a.rec_idx[k]) * a.trace_cols + a.trace_col] =
-                        acc[a.rec_loc[k] * SL + s];
+                        (T)acc[a.rec_loc[k] * SL + s];
                 }
             }
         }
@@ -327,7 +327,7 @@ __global__ void __launch_bounds__(kBlock, sizeof(T) == 8 ? SEM_MIN_WAVES_F64 : S
             const int loc = i / SL, s = i - (i / SL) * SL;
             const int node = nb + loc;
             const int64_t g = (int64_t)node * S + s0 + s;
-            a.r_out[g] = a.mode == 2 ? a.dtminv[node] * acc[i] : acc[i];
+            a.r_out[g] = a.mode == 2 ? a.dtminv[node] * (T)acc[i] : (T)acc[i];
         }
     }
 }
