@@ -658,8 +658,9 @@ int sem_create(const sem_mesh* mesh, const sem_options* opt, sem_ctx** out) {
     po.dt = opt->dt;
     po.cfl = opt->cfl;
     po.tile_elems = opt->tile_elems;
-    // measured on the layered 1024^2 p=4 mesh: FP32 256 threads x 1 pass, FP64 512 x 1 pass
-    const int row_block = opt->block_threads > 0 ? opt->block_threads : (opt->precision == SEM_F64 ? 512 : 256);
+    // measured on the layered 1024^2 p=4 mesh (FP64 LDS accumulators): 512 threads x 1 pass
+    // in both precisions
+    const int row_block = opt->block_threads > 0 ? opt->block_threads : 512;
     if (row_block != 256 && row_block != 512 && row_block != 1024) {
         g_create_error = "block_threads must be 256, 512 or 1024";
         delete c;
