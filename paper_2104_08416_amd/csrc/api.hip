@@ -271,8 +271,8 @@ int upload_geometry(sem_ctx* c) {
     // the kernels address these arrays with 32-bit byte offsets
     const int64_t ni = (int64_t)(P.p - 1) * (P.p - 1);
     const int64_t words = shots_kernel(c) ? 3 * nq + 1 + ni : row_kernel(c) ? 8 : 3 * nq;
-    const int64_t nblk = shots_kernel(c) || row_kernel(c) ? ne : (ne + 63) / 64 * 64;
-    if ((double)nblk * words * sizeof(T) >= 4294967296.0 || (double)nblk * nq * 4.0 >= 4294967296.0)
+    const int64_t n_rec = shots_kernel(c) || row_kernel(c) ? ne : (ne + 63) / 64 * 64;
+    if ((double)n_rec * words * sizeof(T) >= 4294967296.0 || (double)n_rec * nq * 4.0 >= 4294967296.0)
         return fail(c, SEM_ERR_INVALID_ARG, "element arrays exceed 4 GiB (32-bit buffer offsets)");
     if (shots_kernel(c)) {
         // record: g11, g12, g22 per node, c2, then dt/M at the (p-1)^2 element-interior
