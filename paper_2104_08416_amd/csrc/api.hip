@@ -147,10 +147,33 @@ size_t lds_bytes(const sem_ctx* c) {
     return (size_t)c->plan.max_owned * c->SL * sizeof(double);
 }
 
+bool row_kernel(const sem_ctx* c);
+
+// One step-kernel launch over all tiles. The row kernel (one shot lane) keeps the state
+// shot-major [S][N] and is launched once per shot with every per-shot array offset.
 template <typename T>
 int launch(sem_ctx* c, const sem::StepArgs<T>& a) {
     const int64_t nt = (int64_t)c->plan.tile_eb.size() - 1;
-    SEM_HIP(c, sem::launch_step<T>(c->plan.p, c->SL, c->geo, nt, lds_bytes(c), a, c->stream));
+    if (!row_kernel(c) || c->S == 1) {
+        SEM_HIP(c, sem::launch_step<T>(c->plan.p, c->SL, c->geo, nt, lds_bytes(c), a, c->stream));
+        return SEM_OK;
+    }
+    const int64_t nn = c->plan.nn;
+    for (int32_t s = 0; s < c->S; ++s) {
+        sem::StepArgs<T> b = a;
+        b.n_slices = 1;
+        b.shot = s;
+        b.state_bytes = (uint32_t)((size_t)nn * sizeof(T));
+        const int64_t so = (int64_t)s * nn;
+        if (a.u_in) b.u_in = a.u_in + so;
+        if (a.u_out) b.u_out = a.u_out + so;
+        if (a.v) b.v = a.v + so;
+        if (a.r_out) b.r_out = a.r_out + so;
+        if (a.u_pair) b.u_pair = a.u_pair + so;
+        if (a.trace) b.trace = a.trace + (int64_t)s * a.n_rec * a.trace_cols;
+        if (a.inj) b.inj = a.inj + (int64_t)s * a.n_rec * a.inj_cols;
+        SEM_HIP(c, sem::launch_step<T>(c->plan.p, c->SL, c->geo, nt, lds_bytes(c), b, c->stream));
+    }
     return SEM_OK;
 }
 
@@ -346,12 +369,11 @@ int upload_mesh(sem_ctx* c) {
     return zero_state<T>(c);
 }
 
+// 64 shot lanes (one wave per element) when the batch is a multiple of 64; otherwise one
+// lane: the single-shot row kernel, one block per tile and shot
 int pick_shot_lanes(int S, int requested) {
     if (requested > 0) return requested;
-    if (S % 64 == 0) return 64;                   // the 64-shot kernel (one wave per element)
-    int sl = 1;
-    while (sl < 16 && S % (sl * 2) == 0) sl *= 2;
-    return sl;
+    return S % 64 == 0 ? 64 : 1;
 }
 
 // Adaptive tiles: one workgroup pass covers kBlock / shot_lanes elements; single-shot
@@ -473,7 +495,7 @@ int apply_t(sem_ctx* c, const void* u_dev, void* r_dev) {
     int rc = SEM_OK;
     do {
         hipError_t h = sem::launch_nodes_from_original<T>((const T*)u_dev, (T*)tin.p,
-                                                          (const int32_t*)c->n2o_node.p, N, c->S, c->stream);
+                                                          (const int32_t*)c->n2o_node.p, N, c->S, row_kernel(c), c->stream);
         if (h != hipSuccess) { rc = fail(c, SEM_ERR_HIP, hipGetErrorString(h)); break; }
         sem::StepArgs<T> a = base_args<T>(c);
         a.u_in = (const T*)tin.p;
@@ -482,7 +504,7 @@ int apply_t(sem_ctx* c, const void* u_dev, void* r_dev) {
         rc = launch<T>(c, a);
         if (rc) break;
         h = sem::launch_nodes_to_original<T>((const T*)tout.p, (T*)r_dev, (const int32_t*)c->n2o_node.p,
-                                             N, c->S, c->stream);
+                                             N, c->S, row_kernel(c), c->stream);
         if (h != hipSuccess) { rc = fail(c, SEM_ERR_HIP, hipGetErrorString(h)); break; }
         h = hipStreamSynchronize(c->stream);
         if (h != hipSuccess) { rc = fail(c, SEM_ERR_HIP, hipGetErrorString(h)); break; }
@@ -693,8 +715,9 @@ int sem_create(const sem_mesh* mesh, const sem_options* opt, sem_ctx** out) {
         delete c;
         return SEM_ERR_INVALID_ARG;
     }
-    // single shot: row kernel with in-kernel geometry; 64-shot lanes: one wave per element
-    if (c->S == 1) c->geo = row_block * 8 + np;
+    // one shot lane: row kernel with in-kernel geometry (shot-major state, a block per tile
+    // and shot); 64 shot lanes: one wave per element
+    if (c->SL == 1) c->geo = row_block * 8 + np;
     // 64 shots: FP32 512 threads, FP64 256 (p = 4: about 100 VGPRs in FP32, 170 in FP64)
     else if (c->SL == 64)
         c->geo = sem::kGeoShots +
@@ -878,10 +901,12 @@ int sem_get_field(sem_ctx* c, int32_t which, void* dev) {
     const void* src = which == SEM_FIELD_U ? c->u[c->cur].p : c->v.p;
     if (c->precision == SEM_F64)
         SEM_HIP(c, sem::launch_nodes_to_original<double>((const double*)src, (double*)dev,
-                                                         (const int32_t*)c->n2o_node.p, c->plan.nn, c->S, c->stream));
+                                                         (const int32_t*)c->n2o_node.p, c->plan.nn, c->S, row_kernel(c),
+                                                         c->stream));
     else
         SEM_HIP(c, sem::launch_nodes_to_original<float>((const float*)src, (float*)dev,
-                                                        (const int32_t*)c->n2o_node.p, c->plan.nn, c->S, c->stream));
+                                                        (const int32_t*)c->n2o_node.p, c->plan.nn, c->S, row_kernel(c),
+                                                         c->stream));
     return SEM_OK;
 }
 
@@ -894,10 +919,12 @@ int sem_set_field(sem_ctx* c, int32_t which, const void* dev) {
     void* dst = which == SEM_FIELD_U ? c->u[c->cur].p : c->v.p;
     if (c->precision == SEM_F64)
         SEM_HIP(c, sem::launch_nodes_from_original<double>((const double*)dev, (double*)dst,
-                                                           (const int32_t*)c->n2o_node.p, c->plan.nn, c->S, c->stream));
+                                                           (const int32_t*)c->n2o_node.p, c->plan.nn, c->S, row_kernel(c),
+                                                         c->stream));
     else
         SEM_HIP(c, sem::launch_nodes_from_original<float>((const float*)dev, (float*)dst,
-                                                          (const int32_t*)c->n2o_node.p, c->plan.nn, c->S, c->stream));
+                                                          (const int32_t*)c->n2o_node.p, c->plan.nn, c->S, row_kernel(c),
+                                                         c->stream));
     return SEM_OK;
 }
 

@@ -24,7 +24,9 @@ struct StepArgs {
     const T* c2;              // [E]
     const T* dtminv;          // [N] dt / lumped mass
     int64_t E;
-    int32_t S;                // shots (row length of the [N][S] state)
+    int32_t S;                // shots (row length of the [N][S] state; the single-shot
+                              // row kernel keeps [S][N] and is launched once per shot)
+    int32_t shot;             // row kernel: the shot of this launch (sources carry shot ids)
     // byte sizes of the buffers read through bounds-checked buffer loads (each < 4 GiB)
     uint32_t conn_bytes, G_bytes, c2_bytes, state_bytes;
     // tiling
@@ -82,11 +84,11 @@ hipError_t launch_step(int p, int shot_lanes, int geo, int64_t n_tiles, size_t l
 // out[s][old] = in[new][s]  (new -> old node map)
 template <typename T>
 hipError_t launch_nodes_to_original(const T* in, T* out, const int32_t* node_new2old, int64_t N,
-                                    int32_t S, hipStream_t stream);
+                                    int32_t S, bool shot_major, hipStream_t stream);
 // out[new][s] = in[s][old]
 template <typename T>
 hipError_t launch_nodes_from_original(const T* in, T* out, const int32_t* node_new2old, int64_t N,
-                                      int32_t S, hipStream_t stream);
+                                      int32_t S, bool shot_major, hipStream_t stream);
 template <typename T>
 hipError_t launch_fill(T* x, T value, int64_t n, hipStream_t stream);
 template <typename T>

@@ -631,16 +631,12 @@ __global__ void __launch_bounds__(BT) step_shots_kernel(const StepArgs<T> a) {
 // per-element LDS stage written and read by the same wave (LDS executes one wave's
 // instructions in order, so no barrier is needed). Geometric factors come from the six
 // bilinear-map coefficients of the element.
-// Waves per SIMD the row kernel's registers must allow; batching more passes per round of
-// loads keeps more values live, so it trades occupancy for fewer memory round trips.
-template <typename T, int P, int NP>
-constexpr int rows_waves() {
-    return sizeof(T) == 4 ? (NP == 1 ? (P <= 5 ? 8 : 6) : (NP == 2 ? 5 : 3)) : (NP == 1 ? 4 : (NP == 2 ? 3 : 2));
-}
-
-template <typename T, int P, int RB, int NP>
+// GRAD: the adjoint step, which also pairs each element's K_e u with u_pair (a separate
+// instantiation so that the forward step keeps its register budget). Several shots run as
+// one launch per shot, with the state vectors ([S][N], shot-major) offset by the host.
+template <typename T, int P, int RB, int NP, bool GRAD>
 __global__ void __attribute__((amdgpu_flat_work_group_size(RB, RB),
-                               amdgpu_waves_per_eu(rows_waves<T, P, NP>(), 8)))
+                               amdgpu_waves_per_eu(1, 8)))   // registers as the compiler chooses
 step_rows_kernel(const StepArgs<T> a) {
     constexpr int kRowBlock = RB;                      // threads of this workgroup
     constexpr int N = P + 1, NQ = N * N;
@@ -656,6 +652,7 @@ step_rows_kernel(const StepArgs<T> a) {
     T* pre_v = reinterpret_cast<T*>(acc + a.lds_own);
     T* pre_u = pre_v + a.lds_own;
     T* pre_m = pre_u + a.lds_own;
+    T* Dl = pre_m + a.lds_own;                          // D[i*N + j], read per use
 
     const int logical = xcd_logical_block();
     const int tile = logical;
@@ -680,6 +677,7 @@ step_rows_kernel(const StepArgs<T> a) {
         lds_prefetch<RB>(make_rsrc(a.dtminv, a.state_bytes), off, pre_m, ndw);
     }
     for (int i = threadIdx.x; i < nown; i += kRowBlock) acc[i] = 0.0;
+    if (threadIdx.x < NQ) Dl[threadIdx.x] = a.D[threadIdx.x];
     __syncthreads();
 
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -687,22 +685,13 @@ step_rows_kernel(const StepArgs<T> a) {
     const int j = lane - kw * N;                       // row of that element
     const int slot = wave * EPW + kw;
     T* st = stage + slot * NQP;
-    // The row j of a thread never changes: keep row j and column j of D, xi_j and w_j in
-    // registers (selected from the uniform kernel arguments, no per-lane memory reads).
-    T Dj[N], DjT[N], xij = a.xi[0], wj = a.w[0];
-#pragma unroll
-    for (int m = 0; m < N; ++m) {
-        Dj[m] = a.D[m];
-        DjT[m] = a.D[m * N];
-    }
+    // The row j of a thread never changes: xi_j and w_j stay in registers (selected from
+    // the uniform kernel arguments); row j and column j of D are read from LDS per use,
+    // which leaves the registers to the element data (eight waves per SIMD at p = 4).
+    T xij = a.xi[0], wj = a.w[0];
 #pragma unroll
     for (int jj = 1; jj < N; ++jj) {
         if (j == jj) {
-#pragma unroll
-            for (int m = 0; m < N; ++m) {
-                Dj[m] = a.D[jj * N + m];
-                DjT[m] = a.D[m * N + jj];
-            }
             xij = a.xi[jj];
             wj = a.w[jj];
         }
@@ -713,6 +702,9 @@ step_rows_kernel(const StepArgs<T> a) {
         int es[NP], idx[NP][N];
         bool act[NP];
         T bl[NP][8], u[NP][N];
+        T dots[NP];                                    // gradient pairing of this row
+#pragma unroll
+        for (int pp = 0; pp < NP; ++pp) dots[pp] = T(0);
 #pragma unroll
         for (int pp = 0; pp < NP; ++pp) {
             const int k = base + pp * EPB + slot;
@@ -753,7 +745,7 @@ step_rows_kernel(const StepArgs<T> a) {
             }
 #pragma unroll
             for (int m = 0; m < N; ++m) {
-                const T djm = Dj[m];
+                const T djm = Dl[j * N + m];
 #pragma unroll
                 for (int i = 0; i < N; ++i) gy[i] += djm * st[i + N * m];
             }
@@ -765,7 +757,8 @@ step_rows_kernel(const StepArgs<T> a) {
             for (int i = 0; i < N; ++i) {
                 const T xt = bl[pp][1] + bl[pp][2] * a.xi[i];
                 const T yt = bl[pp][4] + bl[pp][5] * a.xi[i];
-                const T sc = (a.w[i] * wj) * recip(xs * yt - xt * ys);
+                // (1/det * w_i) * w_j: no hoisted w_i w_j products held in registers
+                const T sc = (recip(xs * yt - xt * ys) * a.w[i]) * wj;
                 const T g11 = sc * (xt * xt + yt * yt);
                 const T g12 = -sc * (xs * xt + ys * yt);
                 const T g22 = sc * (xs * xs + ys * ys);
@@ -785,16 +778,16 @@ step_rows_kernel(const StepArgs<T> a) {
             for (int i = 0; i < N; ++i) st[i + N * j] = f2[i];
 #pragma unroll
             for (int m = 0; m < N; ++m) {
-                const T dmj = DjT[m];
+                const T dmj = Dl[m * N + j];
 #pragma unroll
                 for (int aa = 0; aa < N; ++aa) r[aa] += dmj * st[aa + N * m];
             }
-            if (a.grad != nullptr && own) {
+            if (GRAD && own) {
                 T dot = T(0);
 #pragma unroll
                 for (int aa = 0; aa < N; ++aa)
                     dot += r[aa] * bload<T>(r_pair, (uint32_t)idx[pp][aa] * (uint32_t)sizeof(T));
-                atomicAdd(&a.grad[e], (double)dot);
+                dots[pp] = dot;
             }
             // Element-interior nodes (0 < a, j < p) belong to this element alone: a plain
             // LDS store; nodes on element edges and corners are shared and need atomics.
@@ -808,6 +801,17 @@ step_rows_kernel(const StepArgs<T> a) {
                 }
             }
         }
+        if (GRAD) {
+            // all lanes active again: sum the N rows of each element, one atomic per element
+#pragma unroll
+            for (int pp = 0; pp < NP; ++pp) {
+                T tot = T(0);
+#pragma unroll
+                for (int m = 0; m < N; ++m) tot += __shfl(dots[pp], kw * N + m, 64);
+                if (j == 0 && act[pp] && base + pp * EPB + slot < n_own_el)
+                    atomicAdd(&a.grad[es[pp]], (double)tot);
+            }
+        }
     }
     __builtin_amdgcn_s_waitcnt(0);                     // this wave's LDS prefetches landed
     __syncthreads();
@@ -817,7 +821,7 @@ step_rows_kernel(const StepArgs<T> a) {
         if (se > sb) {
             const T amp = (T)ricker(a.src_t, a.f0, a.t0);
             for (int i = sb + threadIdx.x; i < se; i += kRowBlock)
-                if (a.src_shot[i] == 0) atomicAdd(&acc[a.src_loc[i]], -(double)(a.src_w[i] * amp));
+                if (a.src_shot[i] == a.shot) atomicAdd(&acc[a.src_loc[i]], -(double)(a.src_w[i] * amp));
             __syncthreads();
         }
     }
@@ -869,10 +873,11 @@ hipError_t launch_one(int64_t n_tiles, size_t lds, const StepArgs<T>& a, hipStre
 
 template <typename T, int P, int RB, int NP>
 hipError_t launch_rows(int64_t n_tiles, size_t lds, const StepArgs<T>& a, hipStream_t st) {
-    auto fn = step_rows_kernel<T, P, RB, NP>;
+    auto fn = a.grad != nullptr ? step_rows_kernel<T, P, RB, NP, true> : step_rows_kernel<T, P, RB, NP, false>;
     constexpr int N = P + 1, NQP = (N * N + 3) & ~3, EPB = (64 / N) * (RB / 64);
-    // stage + accumulator + three prefetch arrays of a.lds_own entries each
-    lds = (size_t)EPB * NQP * sizeof(T) + (size_t)a.lds_own * sizeof(double) + (size_t)3 * a.lds_own * sizeof(T);
+    // stage + accumulator + three prefetch arrays of a.lds_own entries each + D
+    lds = (size_t)EPB * NQP * sizeof(T) + (size_t)a.lds_own * sizeof(double) + (size_t)3 * a.lds_own * sizeof(T) +
+          (size_t)N * N * sizeof(T);
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -930,22 +935,25 @@ hipError_t launch_p(int sl, int geo, int64_t nt, size_t lds, const StepArgs<T>& 
 }
 
 // ------------------------------------------------------------------ utility kernels
+// internal state index i: node-major (node * S + s) or shot-major (s * N + node)
 template <typename T>
-__global__ void to_original_kernel(const T* in, T* out, const int32_t* n2o, int64_t N, int32_t S) {
+__global__ void to_original_kernel(const T* in, T* out, const int32_t* n2o, int64_t N, int32_t S,
+                                   bool shot_major) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N * S) return;
-    const int64_t node = i / S;
-    const int s = (int)(i - node * S);
-    out[(int64_t)s * N + n2o[node]] = in[i];
+    const int64_t node = shot_major ? i % N : i / S;
+    const int64_t s = shot_major ? i / N : i - node * S;
+    out[s * N + n2o[node]] = in[i];
 }
 
 template <typename T>
-__global__ void from_original_kernel(const T* in, T* out, const int32_t* n2o, int64_t N, int32_t S) {
+__global__ void from_original_kernel(const T* in, T* out, const int32_t* n2o, int64_t N, int32_t S,
+                                     bool shot_major) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N * S) return;
-    const int64_t node = i / S;
-    const int s = (int)(i - node * S);
-    out[i] = in[(int64_t)s * N + n2o[node]];
+    const int64_t node = shot_major ? i % N : i / S;
+    const int64_t s = shot_major ? i / N : i - node * S;
+    out[i] = in[s * N + n2o[node]];
 }
 
 template <typename T>
@@ -1015,15 +1023,17 @@ hipError_t launch_step(int p, int sl, int geo, int64_t nt, size_t lds, const Ste
 
 template <typename T>
 hipError_t launch_nodes_to_original(const T* in, T* out, const int32_t* n2o, int64_t N, int32_t S,
-                                    hipStream_t st) {
-    hipLaunchKernelGGL(to_original_kernel<T>, dim3(grid_for(N * S)), dim3(kBlock), 0, st, in, out, n2o, N, S);
+                                    bool shot_major, hipStream_t st) {
+    hipLaunchKernelGGL(to_original_kernel<T>, dim3(grid_for(N * S)), dim3(kBlock), 0, st, in, out, n2o, N, S,
+                       shot_major);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_nodes_from_original(const T* in, T* out, const int32_t* n2o, int64_t N, int32_t S,
-                                      hipStream_t st) {
-    hipLaunchKernelGGL(from_original_kernel<T>, dim3(grid_for(N * S)), dim3(kBlock), 0, st, in, out, n2o, N, S);
+                                      bool shot_major, hipStream_t st) {
+    hipLaunchKernelGGL(from_original_kernel<T>, dim3(grid_for(N * S)), dim3(kBlock), 0, st, in, out, n2o, N, S,
+                       shot_major);
     return hipGetLastError();
 }
 
@@ -1054,9 +1064,9 @@ hipError_t launch_grad_to_original(const double* acc, double* out, const int32_t
 #define SEM_INSTANTIATE(T)                                                                        \
     template hipError_t launch_step<T>(int, int, int, int64_t, size_t, const StepArgs<T>&, hipStream_t); \
     template hipError_t launch_nodes_to_original<T>(const T*, T*, const int32_t*, int64_t, int32_t,   \
-                                                    hipStream_t);                                 \
+                                                    bool, hipStream_t);                           \
     template hipError_t launch_nodes_from_original<T>(const T*, T*, const int32_t*, int64_t,        \
-                                                      int32_t, hipStream_t);                      \
+                                                      int32_t, bool, hipStream_t);                \
     template hipError_t launch_fill<T>(T*, T, int64_t, hipStream_t);                              \
     template hipError_t launch_scale<T>(T*, double, int64_t, hipStream_t);                        \
     template hipError_t launch_sumsq<T>(const T*, int64_t, double*, hipStream_t);
