@@ -24,10 +24,25 @@ Readings where the paper is silent or garbled:
     s - floor(s/2) cells before the parity adjustment described in ``gilbert_cells``.
 Morton: cell x on even bits, cell y on odd bits. Lexicographic: generator order.
 Random: stable sort by splitmix64(seed XOR element id).
+
+The paper's two other strategies (Sec. 5, "Node Connectivity" and "Node Distance") walk
+the mesh's nodes from a start node to connected nodes, appending each visited node's
+elements (once) to the element list. Readings:
+  * the walk runs over the mesh vertices (the nodes of the linear mesh), two vertices
+    being connected when they share an element; "very similar to Cuthill-McKee" is read
+    as the Cuthill-McKee breadth-first walk: visit the queue in order and append each
+    visited vertex's unvisited neighbours in ascending priority;
+  * priority: connectivity = vertex degree (distinct other vertices sharing an element),
+    distance = squared distance (x - x0)^2 + (y - y0)^2 to the lower-left corner
+    (x0, y0) = (min x, min y) of the vertices; ties by ascending vertex id;
+  * the walk starts at the vertex of least priority and restarts there (among the
+    unvisited vertices) if the mesh has several components;
+  * a visited vertex appends its not-yet-listed elements in ascending element id.
 """
 from __future__ import annotations
 
 import math
+from collections import deque
 
 import numpy as np
 
@@ -192,8 +207,74 @@ def random_order(n_elements: int, seed: int):
     return np.argsort(key, kind="stable")
 
 
+def vertex_adjacency(quads, n_vertices: int):
+    """Sorted neighbour lists: vertices sharing at least one element, self excluded."""
+    nb = [set() for _ in range(n_vertices)]
+    for q in np.asarray(quads).tolist():
+        for a in q:
+            nb[a].update(q)
+    return [sorted(s - {v}) for v, s in enumerate(nb)]
+
+
+def vertex_elements(quads, n_vertices: int):
+    """Elements of every vertex, ascending."""
+    out = [[] for _ in range(n_vertices)]
+    for e, q in enumerate(np.asarray(quads).tolist()):
+        for a in set(q):
+            out[a].append(e)
+    return out
+
+
+def walk_order(quads, n_vertices: int, priority):
+    """Cuthill-McKee walk over the vertex graph with the given priority (smaller first,
+    ties by vertex id). Returns (element new -> old order, vertex visit order)."""
+    adj = vertex_adjacency(quads, n_vertices)
+    v_el = vertex_elements(quads, n_vertices)
+    key = lambda v: (priority[v], v)
+    starts = sorted(range(n_vertices), key=key)
+    visited = [False] * n_vertices
+    listed = [False] * len(quads)
+    elems, verts = [], []
+    queue = deque()
+    for s in starts:
+        if visited[s]:
+            continue
+        visited[s] = True
+        queue.append(s)
+        while queue:
+            v = queue.popleft()
+            verts.append(v)
+            for e in v_el[v]:
+                if not listed[e]:
+                    listed[e] = True
+                    elems.append(e)
+            fresh = sorted((w for w in adj[v] if not visited[w]), key=key)
+            for w in fresh:
+                visited[w] = True
+                queue.append(w)
+    return np.array(elems, np.int64), np.array(verts, np.int64)
+
+
+def vertex_degree(quads, n_vertices: int):
+    return np.array([len(a) for a in vertex_adjacency(quads, n_vertices)], np.int64)
+
+
+def distance_priority(vxy):
+    """Squared distance of every vertex to the lower-left corner of the vertex set."""
+    vxy = np.asarray(vxy, dtype=np.float64)
+    x0, y0 = vxy[:, 0].min(), vxy[:, 1].min()
+    dx, dy = vxy[:, 0] - x0, vxy[:, 1] - y0
+    return dx * dx + dy * dy
+
+
 def element_order(kind: str, vxy, quads, seed: int = 3):
-    """new -> old element permutation for 'hilbert' | 'morton' | 'lex' | 'random'."""
+    """new -> old element permutation for 'hilbert' | 'morton' | 'lex' | 'random' |
+    'connectivity' | 'distance'."""
+    if kind == "connectivity":
+        nv = np.asarray(vxy).shape[0]
+        return walk_order(quads, nv, vertex_degree(quads, nv))[0]
+    if kind == "distance":
+        return walk_order(quads, np.asarray(vxy).shape[0], distance_priority(vxy))[0]
     if kind == "hilbert":
         return hilbert_order(vxy, quads)
     if kind == "morton":

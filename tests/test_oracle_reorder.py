@@ -4,11 +4,16 @@ The paper states that the generalized Hilbert curve equals the standard one when
 sides are powers of two (Sec. 3); the standard curve is produced here by an independent
 textbook bit-manipulation conversion, not by the oracle's recursive splitter.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
 import workloads
 from oracle import mesh, reorder
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
 def standard_hilbert_d2xy(order: int, d: int):
@@ -165,3 +170,53 @@ def test_first_touch_properties():
         # ...ordered by ascending degree
         assert np.all(np.diff(deg[node[np.sort(fresh)]]) >= 0)
         seen = max(seen, ids.max())
+
+
+# ------------------------------------------------------ the paper's node-walk strategies
+def test_walk_orders_hand_worked_fixture():
+    """Node Connectivity and Node Distance strategies (Sec. 5) on a scrambled 3x1 strip,
+    against orders worked by hand (tests/golden/walk_orders_strip3.json)."""
+    g = json.load(open(os.path.join(GOLDEN, "walk_orders_strip3.json")))
+    vxy, quads = np.array(g["vxy"], float), np.array(g["quads"])
+    nv = vxy.shape[0]
+    np.testing.assert_array_equal(reorder.vertex_degree(quads, nv), g["degree"])
+    for kind, prio in (("connectivity", reorder.vertex_degree(quads, nv)),
+                       ("distance", reorder.distance_priority(vxy))):
+        el, vt = reorder.walk_order(quads, nv, prio)
+        np.testing.assert_array_equal(el, g[kind]["elements"], err_msg=kind)
+        np.testing.assert_array_equal(vt, g[kind]["vertices"], err_msg=kind)
+        np.testing.assert_array_equal(reorder.element_order(kind, vxy, quads), g[kind]["elements"])
+
+
+@pytest.mark.parametrize("kind", ["connectivity", "distance"])
+def test_walk_orders_are_breadth_first(kind):
+    """On a jittered 13x9 grid: the vertex visit order is a breadth-first order from the
+    start vertex (hop counts never decrease, checked against scipy's shortest paths); the
+    start has the least priority; every element is listed when its first vertex is
+    visited, elements of one vertex in ascending id."""
+    from scipy.sparse import coo_matrix
+    from scipy.sparse.csgraph import shortest_path
+    vxy, quads, _, _ = workloads.grid_mesh(13, 9, 1300.0, 900.0, jitter=0.2, seed=5)
+    nv = vxy.shape[0]
+    prio = reorder.vertex_degree(quads, nv) if kind == "connectivity" else reorder.distance_priority(vxy)
+    el, vt = reorder.walk_order(quads, nv, prio)
+    assert sorted(el.tolist()) == list(range(quads.shape[0]))
+    assert sorted(vt.tolist()) == list(range(nv))
+    best = min(range(nv), key=lambda v: (prio[v], v))
+    assert vt[0] == best
+    rows, cols = [], []
+    for q in quads.tolist():
+        for a in q:
+            for b in q:
+                if a != b:
+                    rows.append(a)
+                    cols.append(b)
+    A = coo_matrix((np.ones(len(rows)), (rows, cols)), shape=(nv, nv)).tocsr()
+    hops = shortest_path(A, unweighted=True, indices=[vt[0]])[0]
+    assert np.all(np.diff(hops[vt]) >= 0)
+    pos = np.empty(nv, np.int64)
+    pos[vt] = np.arange(nv)
+    first = np.array([pos[q].min() for q in quads[el]])
+    assert np.all(np.diff(first) >= 0)
+    same = np.diff(first) == 0
+    assert np.all(np.diff(el)[same] > 0)

@@ -87,7 +87,7 @@ def test_snap_ties_go_to_lowest_id():
     assert solver.snap_to_nodes([[1.0, 0.0]], xy)[0] == 0
 
 
-@pytest.mark.parametrize("kind", ["hilbert", "morton", "random"])
+@pytest.mark.parametrize("kind", ["hilbert", "morton", "random", "connectivity", "distance"])
 def test_relabelling_leaves_traces_unchanged(kind):
     """The reordering is a relabelling (Sec. 4.3): running the SEM on the reordered
     element list and mapping back gives the unordered result to rounding."""
