@@ -243,7 +243,8 @@ def main():
     ap.add_argument("--legs", default=",".join(ALL_LEGS))
     ap.add_argument("--quick", action="store_true", help="headline leg only")
     ap.add_argument("--n", type=int, default=None, help="elements per side of the headline mesh")
-    ap.add_argument("--order", default="hilbert", choices=["hilbert", "morton", "lex", "random"],
+    ap.add_argument("--order", default="hilbert",
+                    choices=["hilbert", "morton", "lex", "random", "connectivity", "distance"],
                     help="element order of the headline leg")
     ap.add_argument("--precision", default="f32", choices=["f32", "f64"], help="headline precision")
     ap.add_argument("--workload", default="layered1024", choices=["layered1024", "graded1414", "batch512"],
@@ -307,7 +308,7 @@ def main():
     if "orders" in legs:
         out["orders"] = {"hilbert": {k: main_leg[k] for k in ("gdof_steps_per_s", "hbm_frac", "halo_ratio",
                                                               "setup_s", "reorder_s")}}
-        for order in ("morton", "lex", "random"):
+        for order in ("morton", "lex", "random", "connectivity", "distance"):
             log(f"[bench] order {order}")
             so, _ = make_sim(sem, wl, "f32", order)
             spo, _ = time_steps(torch, so, min(args.steps, 200), 5)

@@ -49,8 +49,13 @@ enum sem_status {
 };
 
 enum sem_precision { SEM_F32 = 0, SEM_F64 = 1 };
+/* Element orders: the generalized Hilbert curve (Sec. 4.3), Morton, lexicographic (input),
+ * random (splitmix64 of seed ^ id), and the benchmark section's node-walk strategies
+ * (Sec. 5): Node Connectivity and Node Distance, breadth-first walks over the mesh
+ * vertices keyed on vertex degree or on the distance to the lower-left corner, each
+ * visited vertex listing its not-yet-listed elements in ascending id. */
 enum sem_elem_order { SEM_ORDER_HILBERT = 0, SEM_ORDER_MORTON = 1, SEM_ORDER_LEX = 2,
-                      SEM_ORDER_RANDOM = 3 };
+                      SEM_ORDER_RANDOM = 3, SEM_ORDER_CONNECTIVITY = 4, SEM_ORDER_DISTANCE = 5 };
 enum sem_node_order { SEM_NODES_FIRST_TOUCH = 0, SEM_NODES_ORIGINAL = 1 };
 enum sem_field { SEM_FIELD_U = 0, SEM_FIELD_V = 1 };
 

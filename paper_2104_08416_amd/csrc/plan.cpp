@@ -289,6 +289,79 @@ int32_t nearest_node(const Plan& plan, double px, double py) {
     return best;
 }
 
+// Element order of the benchmark section's node-walk strategies (Sec. 5): a breadth-first
+// (Cuthill-McKee) walk over the mesh vertices, two vertices being neighbours when they
+// share an element. The walk starts at the vertex of least priority (restarting there
+// among unvisited vertices for further components) and queues each visited vertex's
+// unvisited neighbours in ascending (priority, id); every visited vertex lists its
+// not-yet-listed elements in ascending id. Priority: the vertex degree (distinct
+// neighbours) or, with by_distance, the squared distance to (min x, min y).
+static std::vector<int32_t> vertex_walk(const MeshIn& m, bool by_distance) {
+    const int64_t nv = m.nv, ne = m.ne;
+    // elements of every vertex, ascending (corners of a valid quad are distinct)
+    std::vector<int32_t> v2e_b(nv + 1, 0), v2e((size_t)ne * 4);
+    for (int64_t i = 0; i < ne * 4; ++i) v2e_b[m.quad[i] + 1]++;
+    for (int64_t v = 0; v < nv; ++v) v2e_b[v + 1] += v2e_b[v];
+    {
+        std::vector<int32_t> fill(v2e_b.begin(), v2e_b.end() - 1);
+        for (int64_t e = 0; e < ne; ++e)
+            for (int k = 0; k < 4; ++k) v2e[fill[m.quad[4 * e + k]]++] = (int32_t)e;
+    }
+    std::vector<int32_t> stamp(nv, -1), nbr;
+    auto neighbours = [&](int32_t v) {
+        nbr.clear();
+        stamp[v] = v;
+        for (int32_t i = v2e_b[v]; i < v2e_b[v + 1]; ++i)
+            for (int k = 0; k < 4; ++k) {
+                const int32_t w = m.quad[4 * (int64_t)v2e[i] + k];
+                if (stamp[w] != v) { stamp[w] = v; nbr.push_back(w); }
+            }
+    };
+    std::vector<double> prio(nv);
+    if (by_distance) {
+        double x0 = INFINITY, y0 = INFINITY;
+        for (int64_t v = 0; v < nv; ++v) {
+            x0 = std::min(x0, m.vxy[2 * v]);
+            y0 = std::min(y0, m.vxy[2 * v + 1]);
+        }
+        for (int64_t v = 0; v < nv; ++v) {
+            const double dx = m.vxy[2 * v] - x0, dy = m.vxy[2 * v + 1] - y0;
+            prio[v] = dx * dx + dy * dy;
+        }
+    } else {
+        for (int64_t v = 0; v < nv; ++v) {
+            neighbours((int32_t)v);
+            prio[v] = (double)nbr.size();
+        }
+        std::fill(stamp.begin(), stamp.end(), -1);
+    }
+    auto before = [&](int32_t a, int32_t b) { return prio[a] < prio[b] || (prio[a] == prio[b] && a < b); };
+    std::vector<int32_t> starts(nv);
+    std::iota(starts.begin(), starts.end(), 0);
+    std::sort(starts.begin(), starts.end(), before);
+    std::vector<uint8_t> visited(nv, 0), listed(ne, 0);
+    std::vector<int32_t> queue, order;
+    queue.reserve(nv);
+    order.reserve(ne);
+    for (int32_t s : starts) {
+        if (visited[s]) continue;
+        visited[s] = 1;
+        queue.clear();
+        queue.push_back(s);
+        for (size_t head = 0; head < queue.size(); ++head) {
+            const int32_t v = queue[head];
+            for (int32_t i = v2e_b[v]; i < v2e_b[v + 1]; ++i)
+                if (!listed[v2e[i]]) { listed[v2e[i]] = 1; order.push_back(v2e[i]); }
+            neighbours(v);
+            size_t k0 = queue.size();
+            for (int32_t w : nbr)
+                if (!visited[w]) { visited[w] = 1; queue.push_back(w); }
+            std::sort(queue.begin() + k0, queue.end(), before);
+        }
+    }
+    return order;
+}
+
 void build_tiles(Plan& P, int tile_elems, int tile_items, int max_owned, bool split_single) {
     const int64_t ne = P.ne, nq = P.nq;
     // node -> incident elements (new numbering)
@@ -415,7 +488,7 @@ std::string build_plan(const MeshIn& m, const PlanOptions& opt, Plan& P, int& co
     code = SEM_ERR_INVALID_ARG;
     if (opt.p < 1 || opt.p > 7) return "p must be in 1..7";
     if (m.ne < 1 || m.nv < 4 || !m.vxy || !m.quad || !m.c2) return "empty or null mesh";
-    if (opt.elem_order < 0 || opt.elem_order > 3) return "unknown element order";
+    if (opt.elem_order < 0 || opt.elem_order > 5) return "unknown element order";
     if (opt.node_order < 0 || opt.node_order > 1) return "unknown node order";
     if (opt.tile_elems < 0 || (opt.tile_elems == 0 && opt.tile_items < 1)) return "bad tile size";
     for (int64_t e = 0; e < m.ne; ++e)
@@ -520,6 +593,9 @@ std::string build_plan(const MeshIn& m, const PlanOptions& opt, Plan& P, int& co
         }
     } else if (opt.elem_order == SEM_ORDER_RANDOM) {
         for (int64_t e = 0; e < ne; ++e) key[e] = splitmix64(opt.seed ^ (uint64_t)e);
+    } else if (opt.elem_order == SEM_ORDER_CONNECTIVITY || opt.elem_order == SEM_ORDER_DISTANCE) {
+        const std::vector<int32_t> walk = vertex_walk(m, opt.elem_order == SEM_ORDER_DISTANCE);
+        for (int64_t k = 0; k < ne; ++k) key[walk[k]] = (uint64_t)k;
     } else {
         for (int64_t e = 0; e < ne; ++e) key[e] = (uint64_t)e;
     }

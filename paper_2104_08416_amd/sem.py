@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsem_hip.so")
 
 F32, F64 = 0, 1
-ORDERS = {"hilbert": 0, "morton": 1, "lex": 2, "random": 3}
+ORDERS = {"hilbert": 0, "morton": 1, "lex": 2, "random": 3, "connectivity": 4, "distance": 5}
 NODE_ORDERS = {"first_touch": 0, "original": 1}
 FIELD_U, FIELD_V = 0, 1
 STATUS = {0: "OK", -1: "INVALID_ARG", -2: "BAD_MESH", -3: "UNSTABLE_DT", -4: "HIP_ERROR",

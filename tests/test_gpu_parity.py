@@ -58,7 +58,7 @@ def test_fp64_homog64_full_size(semlib, gpu_ok, order):
     assert np.abs(tr - tr_o).max() <= 1e-12 * np.abs(u_o).max()
 
 
-@pytest.mark.parametrize("order", ["hilbert", "morton", "lex", "random"])
+@pytest.mark.parametrize("order", ["hilbert", "morton", "lex", "random", "connectivity", "distance"])
 def test_fp64_layered_ragged_tiles(semlib, gpu_ok, order):
     """30 x 30 jittered layered mesh with 64-element tiles: 15 tiles, a ragged last tile,
     halos across tile borders; source close enough that receivers see the wave."""

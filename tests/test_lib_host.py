@@ -2,6 +2,7 @@
 oracle's independent reorder (Sec. 4.3), the Hilbert key function against the oracle's
 curve enumeration, node snapping, dt, and error paths forced from the host."""
 import ctypes
+import json
 import os
 import re
 
@@ -29,10 +30,10 @@ def _oracle_perm(wl, kind, seed=3):
     return reorder.reorder(kind, wl.vxy, wl.quads, conn, seed=seed)
 
 
-CASES = [("homog64", dict(), ("hilbert", "lex", "random")),
-         ("layered1024", dict(n=30), ("hilbert", "morton", "lex", "random")),
-         ("graded1414", dict(n=40, p=5), ("hilbert", "morton", "random")),
-         ("batch512", dict(n=48), ("hilbert", "random"))]
+CASES = [("homog64", dict(), ("hilbert", "lex", "random", "connectivity", "distance")),
+         ("layered1024", dict(n=30), ("hilbert", "morton", "lex", "random", "connectivity", "distance")),
+         ("graded1414", dict(n=40, p=5), ("hilbert", "morton", "random", "connectivity", "distance")),
+         ("batch512", dict(n=48), ("hilbert", "random", "connectivity", "distance"))]
 
 
 @pytest.mark.parametrize("name,kw,orders", CASES)
@@ -172,3 +173,15 @@ def test_autotune_needs_device(semlib):
     with pytest.raises(semlib.SemError) as ei:
         semlib.autotune(wl.vxy, wl.quads, wl.c2, wl.p, device=-1, stream=0)
     assert ei.value.status == "NO_DEVICE"
+
+
+@pytest.mark.parametrize("kind", ["connectivity", "distance"])
+def test_walk_orders_on_hand_worked_strip(semlib, kind):
+    """The library's node-walk element orders on the scrambled 3x1 strip worked by hand."""
+    g = json.load(open(os.path.join(ROOT, "tests", "golden", "walk_orders_strip3.json")))
+    vxy, quads = np.array(g["vxy"], float), np.array(g["quads"], np.int32)
+    s = semlib.Simulator(vxy, quads, np.full(3, 1.0), 2, order=kind, device=-1)
+    e, _ = s.permutations()
+    s.close()
+    np.testing.assert_array_equal(e, g[kind]["elements"])
+
