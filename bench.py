@@ -7,7 +7,8 @@ stiffness, scatter-add, diagonal-mass-inverse leapfrog update, source and receiv
 
 Extra legs on the same JSON line: the FP64 step on the same mesh, the 64-shot FP32 batch
 and single-shot FP64 step on the 512 x 512 mesh, the adjoint-gradient cost ratio on the
-8-shot inversion workload, and the element-order sweep. The ``cpu_baseline`` leg times the
+8-shot inversion workload, the element-order sweep, and the graded 1414 x 1414 p=5 mesh
+in Hilbert, Morton and random order. The ``cpu_baseline`` leg times the
 FP64 CPU oracle on a bounded section of the headline workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--quick] [--legs main,fp64,...]
@@ -40,7 +41,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
-ALL_LEGS = ("main", "fp64", "batch", "adjoint", "orders", "cpu")
+ALL_LEGS = ("main", "fp64", "batch", "adjoint", "orders", "graded", "cpu")
 KERNEL_SOURCES = ("kernels.hip", "kernels.h", "api.hip", "plan.cpp", "plan.h")
 HEADLINE_PROFILE = os.path.join(ROOT, "profiles", "step_rows_kernel_layered1024_f32_hilbert.md")
 COPY_BYTES = 1 << 30           # the calibration copy reads and writes 1 GiB each
@@ -316,6 +317,17 @@ def main():
             out["orders"][order] = {k: lg[k] for k in ("gdof_steps_per_s", "hbm_frac", "halo_ratio",
                                                        "setup_s", "reorder_s")}
             so.close()
+    if "graded" in legs:
+        log("[bench] graded leg: 1414^2 quads graded 1:8, p=5, FP32, Hilbert / Morton / random")
+        wg = workloads.workload("graded1414")
+        out["graded"] = {}
+        for order in ("hilbert", "morton", "random"):
+            sg, _ = make_sim(sem, wg, "f32", order)
+            spg, _ = time_steps(torch, sg, min(args.steps, 100), 5)
+            lg = leg_summary(sg, spg, f"graded1414 p5 f32 {order}")
+            out["graded"][order] = {k: lg[k] for k in ("gdof_steps_per_s", "us_per_step", "hbm_frac",
+                                                       "halo_ratio", "setup_s", "reorder_s")}
+            sg.close()
     if "batch" in legs:
         log("[bench] batch leg: 512^2 p=4, 64 shots FP32 vs single-shot FP64")
         wb = workloads.workload("batch512")
