@@ -58,6 +58,13 @@ enum sem_elem_order { SEM_ORDER_HILBERT = 0, SEM_ORDER_MORTON = 1, SEM_ORDER_LEX
                       SEM_ORDER_RANDOM = 3, SEM_ORDER_CONNECTIVITY = 4, SEM_ORDER_DISTANCE = 5 };
 enum sem_node_order { SEM_NODES_FIRST_TOUCH = 0, SEM_NODES_ORIGINAL = 1 };
 enum sem_field { SEM_FIELD_U = 0, SEM_FIELD_V = 1 };
+/* SEM_FORM_LEAPFROG: u_tt = div(c^2 grad u) + s, unweighted lumped mass, leapfrog.
+ * SEM_FORM_HEUN: the paper's first-order system (Sec. 4.1-4.2.1) with rho = 1, K = c^2:
+ * (1/c^2) u_t = div v + s, v_t = grad u, v stored per element at its GLL nodes, lumped
+ * mass weighted by 1/c^2, Heun predictor-corrector (two operator evaluations per step).
+ * Single shot only; sources enter as y(t) in the u equation; no adjoint; SEM_FIELD_V is
+ * not available (v is element-local). */
+enum sem_formulation { SEM_FORM_LEAPFROG = 0, SEM_FORM_HEUN = 1 };
 
 /* Input mesh (host arrays, original numbering). */
 typedef struct {
@@ -90,6 +97,7 @@ typedef struct {
     int32_t lds_bytes;       /* LDS budget of a tile's owned-node accumulator, bytes,    *
                               * <= 163840 (the 64-shot kernel accumulates in FP64 in    *
                               * either precision); 0 = automatic                        */
+    int32_t formulation;     /* sem_formulation                                         */
 } sem_options;
 
 typedef struct {
@@ -172,7 +180,8 @@ int sem_run(sem_ctx* ctx, int64_t nsteps, void* traces_dev);
 int sem_step(sem_ctx* ctx);
 
 /* Copy the current field out of / into the context: device buffer [n_shots][n_nodes] of
- * the context precision, ORIGINAL node numbering. For V the value is v^{n-1/2}. */
+ * the context precision, ORIGINAL node numbering. For V the value is v^{n-1/2}
+ * (SEM_FORM_LEAPFROG only; INVALID_ARG for SEM_FORM_HEUN). */
 int sem_get_field(sem_ctx* ctx, int32_t which, void* dev);
 int sem_set_field(sem_ctx* ctx, int32_t which, const void* dev);
 

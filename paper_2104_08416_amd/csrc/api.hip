@@ -50,6 +50,10 @@ struct sem_ctx {
     double lambda_max = 0.0, dt_stable = 0.0;
     double setup_seconds = 0.0;
     std::vector<DevBuf*> owned;       // every DevBuf to free at destroy
+    // first-order system with Heun (SEM_FORM_HEUN): a third U buffer, V at step start,
+    // predictor and end [2][nq][E] each, and 1 / M-bar weighted by 1/c^2
+    int formulation = SEM_FORM_LEAPFROG;
+    DevBuf u_next, hv[3], minv_w;
     std::vector<DevBuf> extra;        // scratch owned by the adjoint driver
 };
 
@@ -177,9 +181,76 @@ int launch(sem_ctx* c, const sem::StepArgs<T>& a) {
     return SEM_OK;
 }
 
+// One Heun step of the first-order system: predictor (U, V) -> (U~, V~) in u[cur^1], hv[1];
+// corrector from (U~, V~) and (U, V) into u_next, hv[2]; then those become the state.
+template <typename T>
+int heun_step(sem_ctx* c, T* trace, int64_t cols, int64_t col) {
+    const sem::Plan& P = c->plan;
+    sem::HeunArgs<T> a;
+    std::memset(&a, 0, sizeof(a));
+    a.conn = (const int32_t*)c->conn.p;
+    a.G = (const T*)c->G.p;
+    a.minv_w = (const T*)c->minv_w.p;
+    a.E = P.ne;
+    a.conn_bytes = (uint32_t)c->conn.bytes;
+    a.G_bytes = (uint32_t)c->G.bytes;
+    a.state_bytes = (uint32_t)((size_t)P.nn * sizeof(T));
+    a.tile_eb = (const int32_t*)c->tile_eb.p;
+    a.tile_nb = (const int32_t*)c->tile_nb.p;
+    a.halo_b = (const int32_t*)c->halo_b.p;
+    a.halo = (const int32_t*)c->halo.p;
+    for (int i = 0; i < P.n * P.n; ++i) a.D[i] = (T)P.D[i];
+    for (int i = 0; i < P.n; ++i) {
+        a.xi[i] = (T)P.xi[i];
+        a.w[i] = (T)P.w[i];
+    }
+    a.f0 = c->f0;
+    a.t0 = c->t0;
+    if (c->n_src > 0) {
+        a.src_b = (const int32_t*)c->src_b.p;
+        a.src_loc = (const int32_t*)c->src_loc.p;
+        a.src_shot = (const int32_t*)c->src_shot.p;
+        a.src_w = (const T*)c->src_w.p;
+    }
+    const int64_t nt = (int64_t)P.tile_eb.size() - 1;
+    const size_t lds = (size_t)P.max_owned * sizeof(double);
+    const T h = (T)P.dt;
+    // predictor
+    a.u_a = a.u_base = (const T*)c->u[c->cur].p;
+    a.u_out = (T*)c->u[c->cur ^ 1].p;
+    a.v_a = a.v_base = (const T*)c->hv[0].p;
+    a.v_out = (T*)c->hv[1].p;
+    a.alpha = T(1); a.beta = T(0); a.gamma = h;
+    a.src_t = (double)c->step * P.dt;
+    SEM_HIP(c, sem::launch_heun_stage<T>(P.p, nt, lds, a, c->stream));
+    // corrector
+    a.u_a = (const T*)c->u[c->cur ^ 1].p;
+    a.u_base = (const T*)c->u[c->cur].p;
+    a.u_out = (T*)c->u_next.p;
+    a.v_a = (const T*)c->hv[1].p;
+    a.v_base = (const T*)c->hv[0].p;
+    a.v_out = (T*)c->hv[2].p;
+    a.alpha = T(0.5); a.beta = T(0.5); a.gamma = T(0.5) * h;
+    a.src_t = (double)(c->step + 1) * P.dt;
+    if (trace && c->n_rec > 0) {
+        a.rec_b = (const int32_t*)c->rec_b.p;
+        a.rec_loc = (const int32_t*)c->rec_loc.p;
+        a.rec_idx = (const int32_t*)c->rec_idx.p;
+        a.trace = trace;
+        a.trace_cols = cols;
+        a.trace_col = col;
+    }
+    SEM_HIP(c, sem::launch_heun_stage<T>(P.p, nt, lds, a, c->stream));
+    std::swap(c->u[c->cur], c->u_next);
+    std::swap(c->hv[0], c->hv[2]);
+    c->step += 1;
+    return SEM_OK;
+}
+
 // one forward step u[cur] -> u[cur^1]; optional trace column
 template <typename T>
 int do_step(sem_ctx* c, T* trace, int64_t cols, int64_t col) {
+    if (c->formulation == SEM_FORM_HEUN) return heun_step<T>(c, trace, cols, col);
     sem::StepArgs<T> a = base_args<T>(c);
     a.u_in = (const T*)c->u[c->cur].p;
     a.u_out = (T*)c->u[c->cur ^ 1].p;
@@ -212,6 +283,11 @@ int zero_state(sem_ctx* c) {
     const int64_t n = c->plan.nn * (int64_t)c->S;
     for (int k = 0; k < 2; ++k) SEM_HIP(c, sem::launch_fill<T>((T*)c->u[k].p, T(0), n, c->stream));
     SEM_HIP(c, sem::launch_fill<T>((T*)c->v.p, T(0), n, c->stream));
+    if (c->formulation == SEM_FORM_HEUN && c->u_next.p && c->hv[0].p && c->hv[1].p && c->hv[2].p) {
+        const int64_t nvq = 2 * (int64_t)c->plan.nq * c->plan.ne;
+        SEM_HIP(c, sem::launch_fill<T>((T*)c->u_next.p, T(0), n, c->stream));
+        for (int k = 0; k < 3; ++k) SEM_HIP(c, sem::launch_fill<T>((T*)c->hv[k].p, T(0), nvq, c->stream));
+    }
     c->cur = 0;
     c->step = 0;
     return SEM_OK;
@@ -371,6 +447,31 @@ int upload_mesh(sem_ctx* c) {
 
 // 64 shot lanes (one wave per element) when the batch is a multiple of 64; otherwise one
 // lane: the single-shot row kernel, one block per tile and shot
+// First-order system: 1 / M-bar with M-bar_nu = sum over (e, q -> nu) of w_q detJ_q / c_e^2
+// (Eq. A-bar with M = 1/K, rho = 1), new numbering; V buffers and the third U buffer.
+template <typename T>
+int setup_heun(sem_ctx* c) {
+    const sem::Plan& P = c->plan;
+    const int nq = P.nq;
+    std::vector<double> mbar(P.nn, 0.0), g11(nq), g12(nq), g22(nq), det(nq);
+    for (int64_t e = 0; e < P.ne; ++e) {
+        sem::element_geometry(P, c->mesh, e, g11.data(), g12.data(), g22.data(), det.data());
+        const double inv_c2 = 1.0 / c->mesh.c2[e];
+        for (int b = 0; b < P.n; ++b)
+            for (int a = 0; a < P.n; ++a) {
+                const int q = a + P.n * b;
+                mbar[P.conn0[e * nq + q]] += P.w[a] * P.w[b] * det[q] * inv_c2;
+            }
+    }
+    std::vector<double> inv(P.nn);
+    for (int64_t v = 0; v < P.nn; ++v) inv[v] = 1.0 / mbar[P.node_new2old[v]];
+    SEM_HIP(c, upload_real(c, c->minv_w, inv));
+    const size_t nvq = (size_t)2 * nq * P.ne * sizeof(T);
+    for (int k = 0; k < 3; ++k) SEM_HIP(c, dev_alloc(c->hv[k], nvq));
+    SEM_HIP(c, dev_alloc(c->u_next, (size_t)P.nn * sizeof(T)));
+    return zero_state<T>(c);
+}
+
 int pick_shot_lanes(int S, int requested) {
     if (requested > 0) return requested;
     return S % 64 == 0 ? 64 : 1;
@@ -678,6 +779,18 @@ int sem_create(const sem_mesh* mesh, const sem_options* opt, sem_ctx** out) {
     m.vxy = mesh->vxy;
     m.quad = mesh->quad;
     m.c2 = mesh->c2;
+    c->mesh = m;                                  // valid until sem_create returns
+    if (opt->formulation != SEM_FORM_LEAPFROG && opt->formulation != SEM_FORM_HEUN) {
+        g_create_error = "unknown formulation";
+        delete c;
+        return SEM_ERR_INVALID_ARG;
+    }
+    if (opt->formulation == SEM_FORM_HEUN && c->S != 1) {
+        g_create_error = "the first-order (Heun) formulation runs a single shot";
+        delete c;
+        return SEM_ERR_INVALID_ARG;
+    }
+    c->formulation = opt->formulation;
     sem::PlanOptions po;
     po.p = opt->p;
     po.elem_order = opt->elem_order;
@@ -754,6 +867,8 @@ int sem_create(const sem_mesh* mesh, const sem_options* opt, sem_ctx** out) {
     if (!c->host_only) {
         int rc = set_device(c);
         if (rc == SEM_OK) rc = c->precision == SEM_F64 ? upload_mesh<double>(c) : upload_mesh<float>(c);
+        if (rc == SEM_OK && c->formulation == SEM_FORM_HEUN)
+            rc = c->precision == SEM_F64 ? setup_heun<double>(c) : setup_heun<float>(c);
         if (rc == SEM_OK) rc = c->precision == SEM_F64 ? power_iteration<double>(c, 60)
                                                        : power_iteration<float>(c, 60);
         if (rc == SEM_OK && !(c->plan.dt < c->dt_stable)) {
@@ -805,6 +920,15 @@ int sem_get_info(const sem_ctx* c, sem_info* info) {
     const double elem_words = row_kernel(c) ? 8.0
                               : 3.0 * nq + 1.0 + (shots_kernel(c) ? (P.p - 1.0) * (P.p - 1.0) : 0.0);
     info->kernel_bytes_per_step = (double)P.ne * (nq * 4.0 + elem_words * w) + per_node;
+    if (c->formulation == SEM_FORM_HEUN) {
+        // two stages; per element: ids and the 8-word record each stage, V read 1 + 2 times
+        // and written twice (2 nq words each); per node: U read 1 + 2 times, written twice,
+        // 1/M-bar read twice
+        info->alg_bytes_per_step = (double)P.ne * (2.0 * (nq * 4.0 + 8.0 * w) + 5.0 * 2.0 * nq * w) +
+                                   (double)P.nn * 7.0 * w;
+        info->kernel_bytes_per_step = info->alg_bytes_per_step;
+        info->alg_flops_per_step *= 2.0;
+    }
     const double n = (double)P.n;
     info->alg_flops_per_step = (double)P.ne * c->S * (8.0 * n * n * n + 7.0 * n * n) +
                                (double)P.nn * c->S * 4.0;
@@ -853,6 +977,8 @@ int sem_set_receivers(sem_ctx* c, int32_t n, const double* xy, int32_t* node_out
 
 int sem_set_c2(sem_ctx* c, const double* c2) {
     if (!c || !c2) return SEM_ERR_INVALID_ARG;
+    if (c->formulation == SEM_FORM_HEUN)
+        return fail(c, SEM_ERR_INVALID_ARG, "sem_set_c2 is not available for the first-order formulation");
     for (int64_t e = 0; e < c->plan.ne; ++e)
         if (!(c2[e] > 0.0) || !std::isfinite(c2[e])) return fail(c, SEM_ERR_INVALID_ARG, "c2 must be positive");
     for (int64_t k = 0; k < c->plan.ne; ++k) c->plan.c2[k] = c2[c->plan.elem_new2old[k]];
@@ -894,6 +1020,8 @@ int sem_step(sem_ctx* c) { return sem_run(c, 1, nullptr); }
 
 int sem_get_field(sem_ctx* c, int32_t which, void* dev) {
     if (!c || !dev || (which != SEM_FIELD_U && which != SEM_FIELD_V)) return SEM_ERR_INVALID_ARG;
+    if (which == SEM_FIELD_V && c->formulation == SEM_FORM_HEUN)
+        return fail(c, SEM_ERR_INVALID_ARG, "v is element-local in the first-order formulation");
     int rc = need_device(c);
     if (rc) return rc;
     rc = set_device(c);
@@ -912,6 +1040,8 @@ int sem_get_field(sem_ctx* c, int32_t which, void* dev) {
 
 int sem_set_field(sem_ctx* c, int32_t which, const void* dev) {
     if (!c || !dev || (which != SEM_FIELD_U && which != SEM_FIELD_V)) return SEM_ERR_INVALID_ARG;
+    if (which == SEM_FIELD_V && c->formulation == SEM_FORM_HEUN)
+        return fail(c, SEM_ERR_INVALID_ARG, "v is element-local in the first-order formulation");
     int rc = need_device(c);
     if (rc) return rc;
     rc = set_device(c);
@@ -938,6 +1068,8 @@ int sem_apply_stiffness(sem_ctx* c, const void* u_dev, void* r_dev) {
 }
 
 int sem_adjoint_gradient(sem_ctx* c, const void* dL, int64_t nsteps, int32_t ckpt_every, double* grad) {
+    if (c && c->formulation == SEM_FORM_HEUN)
+        return fail(c, SEM_ERR_INVALID_ARG, "no adjoint for the first-order formulation");
     if (!c || !dL || !grad) return SEM_ERR_INVALID_ARG;
     if (nsteps < 1 || ckpt_every < 1) return fail(c, SEM_ERR_INVALID_ARG, "nsteps and ckpt_every must be >= 1");
     int rc = need_device(c);
@@ -1070,7 +1202,7 @@ void sem_destroy(sem_ctx* c) {
         DevBuf* bufs[] = {&c->conn, &c->G, &c->c2, &c->dtminv, &c->tile_eb, &c->tile_nb, &c->tile_ns, &c->halo_b,
                           &c->halo, &c->n2o_node, &c->n2o_elem, &c->u[0], &c->u[1], &c->v,
                           &c->src_b, &c->src_loc, &c->src_shot, &c->src_w, &c->rec_b, &c->rec_loc,
-                          &c->rec_idx};
+                          &c->rec_idx, &c->u_next, &c->hv[0], &c->hv[1], &c->hv[2], &c->minv_w};
         for (DevBuf* b : bufs) dev_free(*b);
     }
     delete c;

@@ -100,4 +100,39 @@ hipError_t launch_sumsq(const T* x, int64_t n, double* out, hipStream_t stream);
 hipError_t launch_grad_to_original(const double* acc, double* out, const int32_t* elem_new2old,
                                    int64_t E, double scale, hipStream_t stream);
 
+// One stage of the first-order u-v system with Heun's scheme (Sec. 4.2, 4.2.1), single
+// shot. For every element (tiles, halo and record layout of the single-shot kernel):
+// V-dot = grad u_a at its local nodes (Eq. v_change, F = I) and R = -sum w detJ V_a .
+// grad N (Eq. u_change_r_effic, B = -I) summed into the owned nodes; then
+//   X_out = alpha X_base + beta X_a + gamma X-dot(X_a)
+// for U (U-dot = M-bar^{-1} (R + y(src_t)), Eq. u_change) and for V. V is element-local,
+// [2][nq][E] (component, local node, element fastest). Predictor: base = a, (1, 0, h);
+// corrector: base = step start, a = predictor, (1/2, 1/2, h/2).
+template <typename T>
+struct HeunArgs {
+    const int32_t* conn;      // [E][nq]
+    const T* G;               // [E][8]: bilinear-map coefficients, c^2, pad
+    const T* minv_w;          // [N] 1 / M-bar (M-bar weighted by 1/c^2)
+    int64_t E;
+    uint32_t conn_bytes, G_bytes, state_bytes;
+    const int32_t *tile_eb, *tile_nb, *halo_b, *halo;
+    const T *u_a, *u_base;
+    T* u_out;
+    const T *v_a, *v_base;
+    T* v_out;
+    T alpha, beta, gamma;
+    const int32_t *src_b, *src_loc, *src_shot;
+    const T* src_w;
+    double src_t, f0, t0;
+    const int32_t *rec_b, *rec_loc, *rec_idx;
+    T* trace;
+    int64_t trace_cols, trace_col;
+    T xi[kMaxP + 1];
+    T w[kMaxP + 1];
+    T D[(kMaxP + 1) * (kMaxP + 1)];
+};
+template <typename T>
+hipError_t launch_heun_stage(int p, int64_t n_tiles, size_t lds_bytes, const HeunArgs<T>& a,
+                             hipStream_t stream);
+
 }  // namespace sem

@@ -959,6 +959,120 @@ hipError_t launch_p(int sl, int geo, int64_t nt, size_t lds, const StepArgs<T>& 
     }
 }
 
+// ---------------------------------------------------------------------------------------
+// First-order u-v system, one Heun stage: one thread per element (own, then halo) of a tile.
+// The element's R is accumulated point by point: at GLL point q = (i, j) the reference
+// derivatives of u give grad u (V-dot, Eq. v_change), and V_a enters R through
+// A_xi = w_i w_j (Vx y_eta - Vy x_eta), A_eta = w_i w_j (Vy x_xi - Vx y_xi) (det J cancels):
+// R(a, b) -= D(i, a) A_xi(i, b) and D(j, b) A_eta(a, j). R is summed into the tile's owned
+// nodes in FP64 LDS words; the owned nodes then take U_out.
+template <typename T, int P>
+__global__ void __launch_bounds__(kBlock) heun_stage_kernel(const HeunArgs<T> a) {
+    constexpr int N = P + 1, NQ = N * N;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    double* acc = reinterpret_cast<double*>(smem_raw);     // [owned nodes]
+    const int tile = xcd_logical_block();
+    const int nb = a.tile_nb[tile];
+    const int nown = a.tile_nb[tile + 1] - nb;
+    const int eb = a.tile_eb[tile];
+    const int n_own_el = a.tile_eb[tile + 1] - eb;
+    const int hb = a.halo_b[tile];
+    const int n_items = n_own_el + (a.halo_b[tile + 1] - hb);
+    const rsrc_t r_conn = make_rsrc(a.conn, a.conn_bytes);
+    const rsrc_t r_G = make_rsrc(a.G, a.G_bytes);
+    const rsrc_t r_u = make_rsrc(a.u_a, a.state_bytes);
+    for (int i = threadIdx.x; i < nown; i += kBlock) acc[i] = 0.0;
+    __syncthreads();
+    for (int k = threadIdx.x; k < n_items; k += kBlock) {
+        const bool own = k < n_own_el;
+        const int e = own ? eb + k : a.halo[hb + k - n_own_el];
+        int idx[NQ];
+        load_ids<NQ>(r_conn, (uint32_t)e * NQ * 4u, idx);
+        T bl[8];
+        load_rec8(r_G, (uint32_t)e * 8u * (uint32_t)sizeof(T), bl);
+        T u[NQ], r[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            u[q] = bload<T>(r_u, (uint32_t)idx[q] * (uint32_t)sizeof(T));
+            r[q] = T(0);
+        }
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            const T xs = bl[0] + bl[2] * a.xi[j];              // x_xi at eta = xi_j
+            const T ys = bl[3] + bl[5] * a.xi[j];
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                const int q = i + N * j;
+                const T xt = bl[1] + bl[2] * a.xi[i];          // x_eta at xi = xi_i
+                const T yt = bl[4] + bl[5] * a.xi[i];
+                T gxi = T(0), geta = T(0);
+#pragma unroll
+                for (int m = 0; m < N; ++m) {
+                    gxi += a.D[i * N + m] * u[m + N * j];
+                    geta += a.D[j * N + m] * u[i + N * m];
+                }
+                const T inv = T(1) / (xs * yt - xt * ys);
+                const T dudx = (yt * gxi - ys * geta) * inv;
+                const T dudy = (xs * geta - xt * gxi) * inv;
+                const int64_t vq = (int64_t)q * a.E + e, vq2 = (int64_t)(NQ + q) * a.E + e;
+                const T vx = a.v_a[vq], vy = a.v_a[vq2];
+                if (own) {
+                    a.v_out[vq] = a.alpha * a.v_base[vq] + a.beta * vx + a.gamma * dudx;
+                    a.v_out[vq2] = a.alpha * a.v_base[vq2] + a.beta * vy + a.gamma * dudy;
+                }
+                const T wij = a.w[i] * a.w[j];
+                const T axi = wij * (vx * yt - vy * xt);
+                const T aeta = wij * (vy * xs - vx * ys);
+#pragma unroll
+                for (int aa = 0; aa < N; ++aa) r[aa + N * j] -= a.D[i * N + aa] * axi;
+#pragma unroll
+                for (int bb = 0; bb < N; ++bb) r[i + N * bb] -= a.D[j * N + bb] * aeta;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int loc = idx[q] - nb;
+            if ((unsigned)loc < (unsigned)nown) atomicAdd(&acc[loc], (double)r[q]);
+        }
+    }
+    __syncthreads();
+    if (a.src_b != nullptr) {
+        const int sb = a.src_b[tile], se = a.src_b[tile + 1];
+        if (se > sb) {
+            const T amp = (T)ricker(a.src_t, a.f0, a.t0);
+            for (int i = sb + threadIdx.x; i < se; i += kBlock)
+                if (a.src_shot[i] == 0) atomicAdd(&acc[a.src_loc[i]], (double)(a.src_w[i] * amp));
+            __syncthreads();
+        }
+    }
+    for (int i = threadIdx.x; i < nown; i += kBlock) {
+        const int node = nb + i;
+        const T un = a.alpha * a.u_base[node] + a.beta * a.u_a[node] + a.gamma * (a.minv_w[node] * (T)acc[i]);
+        a.u_out[node] = un;
+        acc[i] = (double)un;
+    }
+    if (a.trace != nullptr) {
+        const int rb = a.rec_b[tile], re = a.rec_b[tile + 1];
+        if (re > rb) {
+            __syncthreads();
+            for (int i = rb + threadIdx.x; i < re; i += kBlock)
+                a.trace[(int64_t)a.rec_idx[i] * a.trace_cols + a.trace_col] = (T)acc[a.rec_loc[i]];
+        }
+    }
+}
+
+template <typename T, int P>
+hipError_t launch_heun_p(int64_t n_tiles, size_t lds, const HeunArgs<T>& a, hipStream_t st) {
+    auto fn = heun_stage_kernel<T, P>;
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(fn, dim3((unsigned)n_tiles), dim3(kBlock), lds, st, a);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ utility kernels
 // internal state index i: node-major (node * S + s) or shot-major (s * N + node)
 template <typename T>
@@ -1086,6 +1200,20 @@ hipError_t launch_grad_to_original(const double* acc, double* out, const int32_t
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_heun_stage(int p, int64_t nt, size_t lds, const HeunArgs<T>& a, hipStream_t st) {
+    switch (p) {
+        case 1: return launch_heun_p<T, 1>(nt, lds, a, st);
+        case 2: return launch_heun_p<T, 2>(nt, lds, a, st);
+        case 3: return launch_heun_p<T, 3>(nt, lds, a, st);
+        case 4: return launch_heun_p<T, 4>(nt, lds, a, st);
+        case 5: return launch_heun_p<T, 5>(nt, lds, a, st);
+        case 6: return launch_heun_p<T, 6>(nt, lds, a, st);
+        case 7: return launch_heun_p<T, 7>(nt, lds, a, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 #define SEM_INSTANTIATE(T)                                                                        \
     template hipError_t launch_step<T>(int, int, int, int64_t, size_t, const StepArgs<T>&, hipStream_t); \
     template hipError_t launch_nodes_to_original<T>(const T*, T*, const int32_t*, int64_t, int32_t,   \
@@ -1094,7 +1222,8 @@ hipError_t launch_grad_to_original(const double* acc, double* out, const int32_t
                                                       int32_t, bool, hipStream_t);                \
     template hipError_t launch_fill<T>(T*, T, int64_t, hipStream_t);                              \
     template hipError_t launch_scale<T>(T*, double, int64_t, hipStream_t);                        \
-    template hipError_t launch_sumsq<T>(const T*, int64_t, double*, hipStream_t);
+    template hipError_t launch_sumsq<T>(const T*, int64_t, double*, hipStream_t);                 \
+    template hipError_t launch_heun_stage<T>(int, int64_t, size_t, const HeunArgs<T>&, hipStream_t);
 
 SEM_INSTANTIATE(float)
 SEM_INSTANTIATE(double)

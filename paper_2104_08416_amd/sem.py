@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libsem_hip.so")
 F32, F64 = 0, 1
 ORDERS = {"hilbert": 0, "morton": 1, "lex": 2, "random": 3, "connectivity": 4, "distance": 5}
 NODE_ORDERS = {"first_touch": 0, "original": 1}
+FORMULATIONS = {"leapfrog": 0, "heun": 1}
 FIELD_U, FIELD_V = 0, 1
 STATUS = {0: "OK", -1: "INVALID_ARG", -2: "BAD_MESH", -3: "UNSTABLE_DT", -4: "HIP_ERROR",
           -5: "OOM", -6: "NO_DEVICE"}
@@ -42,7 +43,7 @@ class _Options(ctypes.Structure):
                 ("device", ctypes.c_int32), ("dt", ctypes.c_double), ("cfl", ctypes.c_double),
                 ("stream", ctypes.c_void_p), ("tile_elems", ctypes.c_int32), ("shot_lanes", ctypes.c_int32),
                 ("tile_items", ctypes.c_int32), ("block_threads", ctypes.c_int32),
-                ("lds_bytes", ctypes.c_int32)]
+                ("lds_bytes", ctypes.c_int32), ("formulation", ctypes.c_int32)]
 
 
 class _Info(ctypes.Structure):
@@ -136,7 +137,7 @@ class Simulator:
                  n_shots: int = 1, dt: float = 0.0, cfl: float = 0.3, device: int = 0,
                  seed: int = 3, node_order: str = "first_touch", tile_elems: int = 0,
                  shot_lanes: int = 0, tile_items: int = 0, block_threads: int = 0,
-                 lds_bytes: int = 0, stream=None):
+                 lds_bytes: int = 0, formulation: str = "leapfrog", stream=None):
         self._vxy = np.ascontiguousarray(vxy, dtype=np.float64)
         self._quads = np.ascontiguousarray(quads, dtype=np.int32)
         self._c2 = np.ascontiguousarray(c2, dtype=np.float64)
@@ -152,7 +153,7 @@ class Simulator:
             self._torch_device = torch.device("cuda", device)
         o = _Options(p, F64 if precision == "f64" else F32, ORDERS[order], NODE_ORDERS[node_order],
                      seed, n_shots, device, dt, cfl, stream or 0, tile_elems, shot_lanes, tile_items,
-                     block_threads, lds_bytes)
+                     block_threads, lds_bytes, FORMULATIONS[formulation])
         h = ctypes.c_void_p()
         rc = _lib.sem_create(ctypes.byref(m), ctypes.byref(o), ctypes.byref(h))
         if rc:

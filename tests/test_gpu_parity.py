@@ -282,3 +282,30 @@ def test_autotune_picks_a_timed_candidate(semlib, gpu_ok, shots):
         s.close()
     assert np.abs(out[0]).max() > 0
     assert rel(out[0], out[1]) <= 1e-5
+
+
+@pytest.mark.parametrize("prec,tol,nsteps", [("f64", 1e-12, 200), ("f32", 1e-5, 300)])
+def test_heun_first_order_matches_oracle(semlib, gpu_ok, prec, tol, nsteps):
+    """The paper's first-order u-v system with Heun (Sec. 4.2.1) against the FP64 oracle:
+    layered jittered 20x20 mesh, p=4, 40-element tiles (ragged, halos), source and
+    receivers, wavefield and traces."""
+    from oracle import first_order
+    say("case heun", prec)
+    wl = workloads.workload("layered1024", n=20)
+    wl.src_xy = np.array([[5000.0, 8000.0]])
+    fo = first_order.FirstOrderSEM(wl.vxy, wl.quads, wl.c2, wl.p)
+    s = semlib.Simulator(wl.vxy, wl.quads, wl.c2, wl.p, precision=prec, formulation="heun",
+                         tile_elems=40)
+    src = s.set_sources(wl.src_xy, wl.src_shot, wl.f0)
+    rec = s.set_receivers(wl.rec_xy)
+    tr_o, u_o, _ = fo.run(nsteps, s.dt, src, wl.src_shot, wl.f0, rec_nodes=rec)
+    tr = s.run(nsteps).double().cpu().numpy()
+    u = s.get_field(semlib.FIELD_U).double().cpu().numpy()
+    with pytest.raises(semlib.SemError):
+        s.get_field(semlib.FIELD_V)
+    s.close()
+    assert np.abs(u_o).max() > 0
+    err = rel(u, u_o.T)
+    say("heun", prec, "rel L2", err)
+    assert err <= tol
+    assert rel(tr, tr_o) <= tol
