@@ -41,7 +41,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
-ALL_LEGS = ("main", "fp64", "batch", "adjoint", "orders", "graded", "cpu")
+ALL_LEGS = ("main", "fp64", "heun", "batch", "adjoint", "orders", "graded", "cpu")
 KERNEL_SOURCES = ("kernels.hip", "kernels.h", "api.hip", "plan.cpp", "plan.h")
 HEADLINE_PROFILE = os.path.join(ROOT, "profiles", "step_rows_kernel_layered1024_f32_hilbert.md")
 COPY_BYTES = 1 << 30           # the calibration copy reads and writes 1 GiB each
@@ -250,6 +250,8 @@ def main():
     ap.add_argument("--precision", default="f32", choices=["f32", "f64"], help="headline precision")
     ap.add_argument("--workload", default="layered1024", choices=["layered1024", "graded1414", "batch512"],
                     help="headline workload (default: the layered 1024^2 p=4 mesh)")
+    ap.add_argument("--formulation", default="leapfrog", choices=["leapfrog", "heun"],
+                    help="headline formulation: second-order leapfrog or the first-order system with Heun")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     ap.add_argument("--profile-summary", default=None, metavar="DIR",
@@ -292,8 +294,10 @@ def main():
     # ---------------------------------------------------------------- headline
     wl = workloads.workload(args.workload, n=args.n)
     label = f"{args.workload} n={wl.nx} p={wl.p} {args.precision} {args.order} S={wl.n_shots}"
+    if args.formulation != "leapfrog":
+        label += f" {args.formulation}"
     log(f"[bench] headline: {label}, setup ...")
-    sim, t_setup = make_sim(sem, wl, args.precision, args.order)
+    sim, t_setup = make_sim(sem, wl, args.precision, args.order, formulation=args.formulation)
     log(f"[bench] setup {t_setup:.1f} s, timing {args.steps} steps")
     sps, _ = time_steps(torch, sim, args.steps, args.warmup)
     main_leg = leg_summary(sim, sps, label)
@@ -317,6 +321,13 @@ def main():
             out["orders"][order] = {k: lg[k] for k in ("gdof_steps_per_s", "hbm_frac", "halo_ratio",
                                                        "setup_s", "reorder_s")}
             so.close()
+    if "heun" in legs:
+        log("[bench] heun leg: the first-order u-v system with Heun, layered1024 p=4 FP32")
+        sh, _ = make_sim(sem, wl, "f32", "hilbert", formulation="heun")
+        sph, _ = time_steps(torch, sh, min(args.steps, 200), args.warmup)
+        out["heun"] = leg_summary(sh, sph, "layered1024 p4 f32 hilbert S=1 first-order Heun")
+        out["heun"]["time_ratio_vs_leapfrog"] = sph / (main_leg["us_per_step"] / 1e6)
+        sh.close()
     if "graded" in legs:
         log("[bench] graded leg: 1414^2 quads graded 1:8, p=5, FP32, Hilbert / Morton / random")
         wg = workloads.workload("graded1414")
