@@ -967,7 +967,8 @@ hipError_t launch_p(int sl, int geo, int64_t nt, size_t lds, const StepArgs<T>& 
 // R(a, b) -= D(i, a) A_xi(i, b) and D(j, b) A_eta(a, j). R is summed into the tile's owned
 // nodes in FP64 LDS words; the owned nodes then take U_out.
 template <typename T, int P>
-__global__ void __launch_bounds__(kBlock) heun_stage_kernel(const HeunArgs<T> a) {
+__global__ void __attribute__((amdgpu_flat_work_group_size(kBlock, kBlock), amdgpu_waves_per_eu(sizeof(T) == 4 && P <= 4 ? 4 : 1, 8)))
+heun_stage_kernel(const HeunArgs<T> a) {
     constexpr int N = P + 1, NQ = N * N;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     double* acc = reinterpret_cast<double*>(smem_raw);     // [owned nodes]
@@ -981,6 +982,7 @@ __global__ void __launch_bounds__(kBlock) heun_stage_kernel(const HeunArgs<T> a)
     const rsrc_t r_conn = make_rsrc(a.conn, a.conn_bytes);
     const rsrc_t r_G = make_rsrc(a.G, a.G_bytes);
     const rsrc_t r_u = make_rsrc(a.u_a, a.state_bytes);
+    const bool same_base = a.v_base == a.v_a;           // predictor: base and input coincide
     for (int i = threadIdx.x; i < nown; i += kBlock) acc[i] = 0.0;
     __syncthreads();
     for (int k = threadIdx.x; k < n_items; k += kBlock) {
@@ -1017,8 +1019,9 @@ __global__ void __launch_bounds__(kBlock) heun_stage_kernel(const HeunArgs<T> a)
                 const int64_t vq = (int64_t)q * a.E + e, vq2 = (int64_t)(NQ + q) * a.E + e;
                 const T vx = a.v_a[vq], vy = a.v_a[vq2];
                 if (own) {
-                    a.v_out[vq] = a.alpha * a.v_base[vq] + a.beta * vx + a.gamma * dudx;
-                    a.v_out[vq2] = a.alpha * a.v_base[vq2] + a.beta * vy + a.gamma * dudy;
+                    const T bx = same_base ? vx : a.v_base[vq], by = same_base ? vy : a.v_base[vq2];
+                    a.v_out[vq] = a.alpha * bx + a.beta * vx + a.gamma * dudx;
+                    a.v_out[vq2] = a.alpha * by + a.beta * vy + a.gamma * dudy;
                 }
                 const T wij = a.w[i] * a.w[j];
                 const T axi = wij * (vx * yt - vy * xt);
@@ -1029,6 +1032,8 @@ __global__ void __launch_bounds__(kBlock) heun_stage_kernel(const HeunArgs<T> a)
                 for (int bb = 0; bb < N; ++bb) r[i + N * bb] -= a.D[j * N + bb] * aeta;
             }
         }
+        // node ids again (from cache) rather than held in registers through the loop
+        load_ids<NQ>(r_conn, (uint32_t)e * NQ * 4u, idx);
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
             const int loc = idx[q] - nb;
