@@ -106,8 +106,8 @@ hipError_t launch_grad_to_original(const double* acc, double* out, const int32_t
 // grad N (Eq. u_change_r_effic, B = -I) summed into the owned nodes; then
 //   X_out = alpha X_base + beta X_a + gamma X-dot(X_a)
 // for U (U-dot = M-bar^{-1} (R + y(src_t)), Eq. u_change) and for V. V is element-local,
-// [2][nq][E] (component, local node, element fastest). Predictor: base = a, (1, 0, h);
-// corrector: base = step start, a = predictor, (1/2, 1/2, h/2).
+// [E][2][nq] (element, component, local node). Predictor: base = a, (1, 0, h); corrector:
+// base = step start, a = predictor, (1/2, 1/2, h/2). 512 threads, p+1 lanes per element.
 template <typename T>
 struct HeunArgs {
     const int32_t* conn;      // [E][nq]

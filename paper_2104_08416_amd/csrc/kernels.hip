@@ -960,18 +960,24 @@ hipError_t launch_p(int sl, int geo, int64_t nt, size_t lds, const StepArgs<T>& 
 }
 
 // ---------------------------------------------------------------------------------------
-// First-order u-v system, one Heun stage: one thread per element (own, then halo) of a tile.
-// The element's R is accumulated point by point: at GLL point q = (i, j) the reference
-// derivatives of u give grad u (V-dot, Eq. v_change), and V_a enters R through
-// A_xi = w_i w_j (Vx y_eta - Vy x_eta), A_eta = w_i w_j (Vy x_xi - Vx y_xi) (det J cancels):
-// R(a, b) -= D(i, a) A_xi(i, b) and D(j, b) A_eta(a, j). R is summed into the tile's owned
-// nodes in FP64 LDS words; the owned nodes then take U_out.
+// First-order u-v system, one Heun stage. At GLL point (i, j) of an element the reference
+// derivatives of u give grad u = J^-T (d/dxi, d/deta) u (V-dot, Eq. v_change), and V_a
+// enters R through A_xi = w_i w_j (Vx y_eta - Vy x_eta), A_eta = w_i w_j (Vy x_xi - Vx y_xi)
+// (det J cancels): R(a, b) -= D(i, a) A_xi(i, b) and D(j, b) A_eta(a, j). R is summed into
+// the tile's owned nodes in FP64 LDS words; the owned nodes then take U_out.
+// Row-lane Heun stage: the lane layout of step_rows_kernel (p+1 lanes per element, lane j
+// holds row j, a per-element LDS stage exchanges values across rows within the wave).
+// V is element-major [E][2][nq], so a row's p+1 values of a component are contiguous.
 template <typename T, int P>
-__global__ void __attribute__((amdgpu_flat_work_group_size(kBlock, kBlock), amdgpu_waves_per_eu(sizeof(T) == 4 && P <= 4 ? 4 : 1, 8)))
-heun_stage_kernel(const HeunArgs<T> a) {
+__global__ void __launch_bounds__(kRowBlock / 2) heun_rows_kernel(const HeunArgs<T> a) {
+    constexpr int RB = kRowBlock / 2;                  // 512 threads
     constexpr int N = P + 1, NQ = N * N;
+    constexpr int NQP = (NQ + 3) & ~3;
+    constexpr int EPW = 64 / N;
+    constexpr int EPB = EPW * (RB / 64);
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    double* acc = reinterpret_cast<double*>(smem_raw);     // [owned nodes]
+    T* stage = reinterpret_cast<T*>(smem_raw);          // [EPB][NQP]
+    double* acc = reinterpret_cast<double*>(stage + EPB * NQP);   // [owned nodes]
     const int tile = xcd_logical_block();
     const int nb = a.tile_nb[tile];
     const int nown = a.tile_nb[tile + 1] - nb;
@@ -982,62 +988,86 @@ heun_stage_kernel(const HeunArgs<T> a) {
     const rsrc_t r_conn = make_rsrc(a.conn, a.conn_bytes);
     const rsrc_t r_G = make_rsrc(a.G, a.G_bytes);
     const rsrc_t r_u = make_rsrc(a.u_a, a.state_bytes);
-    const bool same_base = a.v_base == a.v_a;           // predictor: base and input coincide
-    for (int i = threadIdx.x; i < nown; i += kBlock) acc[i] = 0.0;
+    const bool same_base = a.v_base == a.v_a;
+    for (int i = threadIdx.x; i < nown; i += RB) acc[i] = 0.0;
     __syncthreads();
-    for (int k = threadIdx.x; k < n_items; k += kBlock) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int kw = lane / N, j = lane - kw * N;
+    const int slot = wave * EPW + kw;
+    T* st = stage + slot * NQP;
+    T xij = a.xi[0], wj = a.w[0];
+#pragma unroll
+    for (int jj = 1; jj < N; ++jj)
+        if (j == jj) {
+            xij = a.xi[jj];
+            wj = a.w[jj];
+        }
+    for (int base = 0; base < n_items; base += EPB) {
+        const int k = base + slot;
+        if (kw >= EPW || k >= n_items) continue;
         const bool own = k < n_own_el;
         const int e = own ? eb + k : a.halo[hb + k - n_own_el];
-        int idx[NQ];
-        load_ids<NQ>(r_conn, (uint32_t)e * NQ * 4u, idx);
+        int idx[N];
+        load_ids<N>(r_conn, (uint32_t)(e * NQ + N * j) * 4u, idx);
         T bl[8];
         load_rec8(r_G, (uint32_t)e * 8u * (uint32_t)sizeof(T), bl);
-        T u[NQ], r[NQ];
+        T u[N], vx[N], vy[N];
+        const int64_t vrow = (int64_t)e * 2 * NQ + N * j;   // component 0 of row j
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            u[q] = bload<T>(r_u, (uint32_t)idx[q] * (uint32_t)sizeof(T));
-            r[q] = T(0);
+        for (int i = 0; i < N; ++i) {
+            u[i] = bload<T>(r_u, (uint32_t)idx[i] * (uint32_t)sizeof(T));
+            vx[i] = a.v_a[vrow + i];
+            vy[i] = a.v_a[vrow + NQ + i];
         }
 #pragma unroll
-        for (int j = 0; j < N; ++j) {
-            const T xs = bl[0] + bl[2] * a.xi[j];              // x_xi at eta = xi_j
-            const T ys = bl[3] + bl[5] * a.xi[j];
+        for (int i = 0; i < N; ++i) st[i + N * j] = u[i];
+        // x_xi, y_xi at eta = xi_j are constant along the row; x_eta, y_eta depend on xi_i
+        const T xs = bl[0] + bl[2] * xij, ys = bl[3] + bl[5] * xij;
+        T r[N], aeta[N];
 #pragma unroll
-            for (int i = 0; i < N; ++i) {
-                const int q = i + N * j;
-                const T xt = bl[1] + bl[2] * a.xi[i];          // x_eta at xi = xi_i
-                const T yt = bl[4] + bl[5] * a.xi[i];
-                T gxi = T(0), geta = T(0);
+        for (int aa = 0; aa < N; ++aa) r[aa] = T(0);
 #pragma unroll
-                for (int m = 0; m < N; ++m) {
-                    gxi += a.D[i * N + m] * u[m + N * j];
-                    geta += a.D[j * N + m] * u[i + N * m];
-                }
-                const T inv = T(1) / (xs * yt - xt * ys);
-                const T dudx = (yt * gxi - ys * geta) * inv;
-                const T dudy = (xs * geta - xt * gxi) * inv;
-                const int64_t vq = (int64_t)q * a.E + e, vq2 = (int64_t)(NQ + q) * a.E + e;
-                const T vx = a.v_a[vq], vy = a.v_a[vq2];
-                if (own) {
-                    const T bx = same_base ? vx : a.v_base[vq], by = same_base ? vy : a.v_base[vq2];
-                    a.v_out[vq] = a.alpha * bx + a.beta * vx + a.gamma * dudx;
-                    a.v_out[vq2] = a.alpha * by + a.beta * vy + a.gamma * dudy;
-                }
-                const T wij = a.w[i] * a.w[j];
-                const T axi = wij * (vx * yt - vy * xt);
-                const T aeta = wij * (vy * xs - vx * ys);
+        for (int i = 0; i < N; ++i) {
+            const T xt = bl[1] + bl[2] * a.xi[i], yt = bl[4] + bl[5] * a.xi[i];
+            T gxi = T(0), geta = T(0);
 #pragma unroll
-                for (int aa = 0; aa < N; ++aa) r[aa + N * j] -= a.D[i * N + aa] * axi;
-#pragma unroll
-                for (int bb = 0; bb < N; ++bb) r[i + N * bb] -= a.D[j * N + bb] * aeta;
+            for (int m = 0; m < N; ++m) {
+                gxi += a.D[i * N + m] * u[m];
+                geta += a.D[j * N + m] * st[i + N * m];
             }
-        }
-        // node ids again (from cache) rather than held in registers through the loop
-        load_ids<NQ>(r_conn, (uint32_t)e * NQ * 4u, idx);
+            const T inv = T(1) / (xs * yt - xt * ys);
+            const T dudx = (yt * gxi - ys * geta) * inv;
+            const T dudy = (xs * geta - xt * gxi) * inv;
+            if (own) {
+                const T bx = same_base ? vx[i] : a.v_base[vrow + i];
+                const T by = same_base ? vy[i] : a.v_base[vrow + NQ + i];
+                a.v_out[vrow + i] = a.alpha * bx + a.beta * vx[i] + a.gamma * dudx;
+                a.v_out[vrow + NQ + i] = a.alpha * by + a.beta * vy[i] + a.gamma * dudy;
+            }
+            const T wij = a.w[i] * wj;
+            const T axi = wij * (vx[i] * yt - vy[i] * xt);
+            aeta[i] = wij * (vy[i] * xs - vx[i] * ys);
+            // along the row: R(aa, j) -= D(i, aa) A_xi(i, j)
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            const int loc = idx[q] - nb;
-            if ((unsigned)loc < (unsigned)nown) atomicAdd(&acc[loc], (double)r[q]);
+            for (int aa = 0; aa < N; ++aa) r[aa] -= a.D[i * N + aa] * axi;
+        }
+        // across rows: R(aa, j) -= sum_m D(m, j) A_eta(aa, m), A_eta exchanged via the stage
+#pragma unroll
+        for (int i = 0; i < N; ++i) st[i + N * j] = aeta[i];
+#pragma unroll
+        for (int m = 0; m < N; ++m) {
+            const T dmj = a.D[m * N + j];
+#pragma unroll
+            for (int aa = 0; aa < N; ++aa) r[aa] -= dmj * st[aa + N * m];
+        }
+        const bool inner_row = j > 0 && j < P;
+#pragma unroll
+        for (int aa = 0; aa < N; ++aa) {
+            const int loc = idx[aa] - nb;
+            if ((unsigned)loc < (unsigned)nown) {
+                if (aa > 0 && aa < P && inner_row) acc[loc] = (double)r[aa];
+                else atomicAdd(&acc[loc], (double)r[aa]);
+            }
         }
     }
     __syncthreads();
@@ -1045,12 +1075,12 @@ heun_stage_kernel(const HeunArgs<T> a) {
         const int sb = a.src_b[tile], se = a.src_b[tile + 1];
         if (se > sb) {
             const T amp = (T)ricker(a.src_t, a.f0, a.t0);
-            for (int i = sb + threadIdx.x; i < se; i += kBlock)
+            for (int i = sb + threadIdx.x; i < se; i += RB)
                 if (a.src_shot[i] == 0) atomicAdd(&acc[a.src_loc[i]], (double)(a.src_w[i] * amp));
             __syncthreads();
         }
     }
-    for (int i = threadIdx.x; i < nown; i += kBlock) {
+    for (int i = threadIdx.x; i < nown; i += RB) {
         const int node = nb + i;
         const T un = a.alpha * a.u_base[node] + a.beta * a.u_a[node] + a.gamma * (a.minv_w[node] * (T)acc[i]);
         a.u_out[node] = un;
@@ -1060,7 +1090,7 @@ heun_stage_kernel(const HeunArgs<T> a) {
         const int rb = a.rec_b[tile], re = a.rec_b[tile + 1];
         if (re > rb) {
             __syncthreads();
-            for (int i = rb + threadIdx.x; i < re; i += kBlock)
+            for (int i = rb + threadIdx.x; i < re; i += RB)
                 a.trace[(int64_t)a.rec_idx[i] * a.trace_cols + a.trace_col] = (T)acc[a.rec_loc[i]];
         }
     }
@@ -1068,13 +1098,15 @@ heun_stage_kernel(const HeunArgs<T> a) {
 
 template <typename T, int P>
 hipError_t launch_heun_p(int64_t n_tiles, size_t lds, const HeunArgs<T>& a, hipStream_t st) {
-    auto fn = heun_stage_kernel<T, P>;
+    constexpr int N = P + 1, NQP = (N * N + 3) & ~3, RB = kRowBlock / 2, EPB = (64 / N) * (RB / 64);
+    auto fn = heun_rows_kernel<T, P>;
+    lds += (size_t)EPB * NQP * sizeof(T);                 // the per-element stage
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(fn, dim3((unsigned)n_tiles), dim3(kBlock), lds, st, a);
+    hipLaunchKernelGGL(fn, dim3((unsigned)n_tiles), dim3(RB), lds, st, a);
     return hipGetLastError();
 }
 
