@@ -199,6 +199,7 @@ int heun_step(sem_ctx* c, T* trace, int64_t cols, int64_t col) {
     a.tile_nb = (const int32_t*)c->tile_nb.p;
     a.halo_b = (const int32_t*)c->halo_b.p;
     a.halo = (const int32_t*)c->halo.p;
+    a.lds_own = (P.max_owned + 63) & ~63;     // prefetch chunks are 64 entries
     for (int i = 0; i < P.n * P.n; ++i) a.D[i] = (T)P.D[i];
     for (int i = 0; i < P.n; ++i) {
         a.xi[i] = (T)P.xi[i];

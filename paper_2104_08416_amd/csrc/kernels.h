@@ -121,6 +121,7 @@ struct HeunArgs {
     const T *v_a, *v_base;
     T* v_out;
     T alpha, beta, gamma;
+    int32_t lds_own;          // owned-node slots of the LDS prefetch arrays (64-aligned)
     const int32_t *src_b, *src_loc, *src_shot;
     const T* src_w;
     double src_t, f0, t0;

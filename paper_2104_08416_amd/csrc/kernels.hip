@@ -978,6 +978,12 @@ __global__ void __launch_bounds__(kRowBlock / 2) heun_rows_kernel(const HeunArgs
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* stage = reinterpret_cast<T*>(smem_raw);          // [EPB][NQP]
     double* acc = reinterpret_cast<double*>(stage + EPB * NQP);   // [owned nodes]
+    // U_base, U_a and 1/M-bar of the owned nodes, prefetched for the update: [3][lds_own]
+    // (FP32 only: in FP64 the 24 bytes per node would halve the blocks resident per CU)
+    constexpr bool PRE = sizeof(T) == 4;
+    T* pre_b = reinterpret_cast<T*>(acc + a.lds_own);
+    T* pre_a = pre_b + a.lds_own;
+    T* pre_m = pre_a + a.lds_own;
     const int tile = xcd_logical_block();
     const int nb = a.tile_nb[tile];
     const int nown = a.tile_nb[tile + 1] - nb;
@@ -989,6 +995,14 @@ __global__ void __launch_bounds__(kRowBlock / 2) heun_rows_kernel(const HeunArgs
     const rsrc_t r_G = make_rsrc(a.G, a.G_bytes);
     const rsrc_t r_u = make_rsrc(a.u_a, a.state_bytes);
     const bool same_base = a.v_base == a.v_a;
+    const bool same_u = a.u_base == a.u_a;             // predictor: U_base is U_a
+    if constexpr (PRE) {
+        const int ndw = nown * (int)(sizeof(T) / 4);
+        const uint32_t off = (uint32_t)nb * (uint32_t)sizeof(T);
+        if (!same_u) lds_prefetch<RB>(make_rsrc(a.u_base, a.state_bytes), off, pre_b, ndw);
+        lds_prefetch<RB>(r_u, off, pre_a, ndw);
+        lds_prefetch<RB>(make_rsrc(a.minv_w, a.state_bytes), off, pre_m, ndw);
+    }
     for (int i = threadIdx.x; i < nown; i += RB) acc[i] = 0.0;
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -1070,6 +1084,7 @@ __global__ void __launch_bounds__(kRowBlock / 2) heun_rows_kernel(const HeunArgs
             }
         }
     }
+    __builtin_amdgcn_s_waitcnt(0);                     // this wave's LDS prefetches landed
     __syncthreads();
     if (a.src_b != nullptr) {
         const int sb = a.src_b[tile], se = a.src_b[tile + 1];
@@ -1082,7 +1097,17 @@ __global__ void __launch_bounds__(kRowBlock / 2) heun_rows_kernel(const HeunArgs
     }
     for (int i = threadIdx.x; i < nown; i += RB) {
         const int node = nb + i;
-        const T un = a.alpha * a.u_base[node] + a.beta * a.u_a[node] + a.gamma * (a.minv_w[node] * (T)acc[i]);
+        T ua, ub, mi;
+        if constexpr (PRE) {
+            ua = pre_a[i];
+            ub = same_u ? ua : pre_b[i];
+            mi = pre_m[i];
+        } else {
+            ua = a.u_a[node];
+            ub = same_u ? ua : a.u_base[node];
+            mi = a.minv_w[node];
+        }
+        const T un = a.alpha * ub + a.beta * ua + a.gamma * (mi * (T)acc[i]);
         a.u_out[node] = un;
         acc[i] = (double)un;
     }
@@ -1100,7 +1125,9 @@ template <typename T, int P>
 hipError_t launch_heun_p(int64_t n_tiles, size_t lds, const HeunArgs<T>& a, hipStream_t st) {
     constexpr int N = P + 1, NQP = (N * N + 3) & ~3, RB = kRowBlock / 2, EPB = (64 / N) * (RB / 64);
     auto fn = heun_rows_kernel<T, P>;
-    lds += (size_t)EPB * NQP * sizeof(T);                 // the per-element stage
+    // stage, accumulator and (FP32) the three prefetch arrays
+    lds = (size_t)EPB * NQP * sizeof(T) + (size_t)a.lds_own * sizeof(double) +
+          (sizeof(T) == 4 ? (size_t)3 * a.lds_own * sizeof(T) : 0);
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
