@@ -50,10 +50,10 @@ struct sem_ctx {
     double lambda_max = 0.0, dt_stable = 0.0;
     double setup_seconds = 0.0;
     std::vector<DevBuf*> owned;       // every DevBuf to free at destroy
-    // first-order system with Heun (SEM_FORM_HEUN): a third U buffer, V at step start,
-    // predictor and end [2][nq][E] each, and 1 / M-bar weighted by 1/c^2
+    // first-order system with Heun (SEM_FORM_HEUN): a third U buffer, V at the start and
+    // the end of a step ([E][2][nq] each), and 1 / M-bar weighted by 1/c^2
     int formulation = SEM_FORM_LEAPFROG;
-    DevBuf u_next, hv[3], minv_w;
+    DevBuf u_next, hv[2], minv_w;
     std::vector<DevBuf> extra;        // scratch owned by the adjoint driver
 };
 
@@ -181,8 +181,8 @@ int launch(sem_ctx* c, const sem::StepArgs<T>& a) {
     return SEM_OK;
 }
 
-// One Heun step of the first-order system: predictor (U, V) -> (U~, V~) in u[cur^1], hv[1];
-// corrector from (U~, V~) and (U, V) into u_next, hv[2]; then those become the state.
+// One Heun step of the first-order system: predictor (U, V) -> U~ in u[cur^1]; corrector
+// from U~ and (U, V) into u_next, hv[1]; then those become the state.
 template <typename T>
 int heun_step(sem_ctx* c, T* trace, int64_t cols, int64_t col) {
     const sem::Plan& P = c->plan;
@@ -217,21 +217,16 @@ int heun_step(sem_ctx* c, T* trace, int64_t cols, int64_t col) {
     const size_t lds = (size_t)P.max_owned * sizeof(double);
     const T h = (T)P.dt;
     // predictor
-    a.u_a = a.u_base = (const T*)c->u[c->cur].p;
+    a.u0 = (const T*)c->u[c->cur].p;
     a.u_out = (T*)c->u[c->cur ^ 1].p;
-    a.v_a = a.v_base = (const T*)c->hv[0].p;
-    a.v_out = (T*)c->hv[1].p;
-    a.alpha = T(1); a.beta = T(0); a.gamma = h;
+    a.v0 = (const T*)c->hv[0].p;
+    a.h = h;
     a.src_t = (double)c->step * P.dt;
-    SEM_HIP(c, sem::launch_heun_stage<T>(P.p, nt, lds, a, c->stream));
+    SEM_HIP(c, sem::launch_heun_stage<T>(P.p, false, nt, lds, a, c->stream));
     // corrector
-    a.u_a = (const T*)c->u[c->cur ^ 1].p;
-    a.u_base = (const T*)c->u[c->cur].p;
+    a.u1 = (const T*)c->u[c->cur ^ 1].p;
     a.u_out = (T*)c->u_next.p;
-    a.v_a = (const T*)c->hv[1].p;
-    a.v_base = (const T*)c->hv[0].p;
-    a.v_out = (T*)c->hv[2].p;
-    a.alpha = T(0.5); a.beta = T(0.5); a.gamma = T(0.5) * h;
+    a.v_out = (T*)c->hv[1].p;
     a.src_t = (double)(c->step + 1) * P.dt;
     if (trace && c->n_rec > 0) {
         a.rec_b = (const int32_t*)c->rec_b.p;
@@ -241,9 +236,9 @@ int heun_step(sem_ctx* c, T* trace, int64_t cols, int64_t col) {
         a.trace_cols = cols;
         a.trace_col = col;
     }
-    SEM_HIP(c, sem::launch_heun_stage<T>(P.p, nt, lds, a, c->stream));
+    SEM_HIP(c, sem::launch_heun_stage<T>(P.p, true, nt, lds, a, c->stream));
     std::swap(c->u[c->cur], c->u_next);
-    std::swap(c->hv[0], c->hv[2]);
+    std::swap(c->hv[0], c->hv[1]);
     c->step += 1;
     return SEM_OK;
 }
@@ -284,10 +279,10 @@ int zero_state(sem_ctx* c) {
     const int64_t n = c->plan.nn * (int64_t)c->S;
     for (int k = 0; k < 2; ++k) SEM_HIP(c, sem::launch_fill<T>((T*)c->u[k].p, T(0), n, c->stream));
     SEM_HIP(c, sem::launch_fill<T>((T*)c->v.p, T(0), n, c->stream));
-    if (c->formulation == SEM_FORM_HEUN && c->u_next.p && c->hv[0].p && c->hv[1].p && c->hv[2].p) {
+    if (c->formulation == SEM_FORM_HEUN && c->u_next.p && c->hv[0].p && c->hv[1].p) {
         const int64_t nvq = 2 * (int64_t)c->plan.nq * c->plan.ne;
         SEM_HIP(c, sem::launch_fill<T>((T*)c->u_next.p, T(0), n, c->stream));
-        for (int k = 0; k < 3; ++k) SEM_HIP(c, sem::launch_fill<T>((T*)c->hv[k].p, T(0), nvq, c->stream));
+        for (int k = 0; k < 2; ++k) SEM_HIP(c, sem::launch_fill<T>((T*)c->hv[k].p, T(0), nvq, c->stream));
     }
     c->cur = 0;
     c->step = 0;
@@ -468,7 +463,7 @@ int setup_heun(sem_ctx* c) {
     for (int64_t v = 0; v < P.nn; ++v) inv[v] = 1.0 / mbar[P.node_new2old[v]];
     SEM_HIP(c, upload_real(c, c->minv_w, inv));
     const size_t nvq = (size_t)2 * nq * P.ne * sizeof(T);
-    for (int k = 0; k < 3; ++k) SEM_HIP(c, dev_alloc(c->hv[k], nvq));
+    for (int k = 0; k < 2; ++k) SEM_HIP(c, dev_alloc(c->hv[k], nvq));
     SEM_HIP(c, dev_alloc(c->u_next, (size_t)P.nn * sizeof(T)));
     return zero_state<T>(c);
 }
@@ -921,18 +916,18 @@ int sem_get_info(const sem_ctx* c, sem_info* info) {
     const double elem_words = row_kernel(c) ? 8.0
                               : 3.0 * nq + 1.0 + (shots_kernel(c) ? (P.p - 1.0) * (P.p - 1.0) : 0.0);
     info->kernel_bytes_per_step = (double)P.ne * (nq * 4.0 + elem_words * w) + per_node;
+    const double n = (double)P.n;
+    info->alg_flops_per_step = (double)P.ne * c->S * (8.0 * n * n * n + 7.0 * n * n) +
+                               (double)P.nn * c->S * 4.0;
     if (c->formulation == SEM_FORM_HEUN) {
-        // two stages; per element: ids and the 8-word record each stage, V read 1 + 2 times
-        // and written twice (2 nq words each); per node: U read 1 + 2 times, written twice,
-        // 1/M-bar read twice
-        info->alg_bytes_per_step = (double)P.ne * (2.0 * (nq * 4.0 + 8.0 * w) + 5.0 * 2.0 * nq * w) +
+        // two stages; per element: ids and the 8-word record each stage, V^n read twice and
+        // V^{n+1} written once (2 nq words each); per node: U^n read twice, U~ written and
+        // read, U^{n+1} written, 1/M-bar read twice
+        info->alg_bytes_per_step = (double)P.ne * (2.0 * (nq * 4.0 + 8.0 * w) + 3.0 * 2.0 * nq * w) +
                                    (double)P.nn * 7.0 * w;
         info->kernel_bytes_per_step = info->alg_bytes_per_step;
         info->alg_flops_per_step *= 2.0;
     }
-    const double n = (double)P.n;
-    info->alg_flops_per_step = (double)P.ne * c->S * (8.0 * n * n * n + 7.0 * n * n) +
-                               (double)P.nn * c->S * 4.0;
     info->setup_seconds = c->setup_seconds;
     info->reorder_seconds = P.reorder_seconds;
     info->max_accum_nodes = P.tile_ns.empty() ? P.max_owned : P.max_shared;
@@ -1203,7 +1198,7 @@ void sem_destroy(sem_ctx* c) {
         DevBuf* bufs[] = {&c->conn, &c->G, &c->c2, &c->dtminv, &c->tile_eb, &c->tile_nb, &c->tile_ns, &c->halo_b,
                           &c->halo, &c->n2o_node, &c->n2o_elem, &c->u[0], &c->u[1], &c->v,
                           &c->src_b, &c->src_loc, &c->src_shot, &c->src_w, &c->rec_b, &c->rec_loc,
-                          &c->rec_idx, &c->u_next, &c->hv[0], &c->hv[1], &c->hv[2], &c->minv_w};
+                          &c->rec_idx, &c->u_next, &c->hv[0], &c->hv[1], &c->minv_w};
         for (DevBuf* b : bufs) dev_free(*b);
     }
     delete c;

@@ -101,13 +101,15 @@ hipError_t launch_grad_to_original(const double* acc, double* out, const int32_t
                                    int64_t E, double scale, hipStream_t stream);
 
 // One stage of the first-order u-v system with Heun's scheme (Sec. 4.2, 4.2.1), single
-// shot. For every element (tiles, halo and record layout of the single-shot kernel):
-// V-dot = grad u_a at its local nodes (Eq. v_change, F = I) and R = -sum w detJ V_a .
-// grad N (Eq. u_change_r_effic, B = -I) summed into the owned nodes; then
-//   X_out = alpha X_base + beta X_a + gamma X-dot(X_a)
-// for U (U-dot = M-bar^{-1} (R + y(src_t)), Eq. u_change) and for V. V is element-local,
-// [E][2][nq] (element, component, local node). Predictor: base = a, (1, 0, h); corrector:
-// base = step start, a = predictor, (1/2, 1/2, h/2). 512 threads, p+1 lanes per element.
+// shot, tiles, halo and record layout of the single-shot kernel. V-dot = grad u at the local
+// nodes of an element (Eq. v_change, F = I); R = -sum w detJ V . grad N (Eq. u_change_r_effic,
+// B = -I) summed into the owned nodes; U-dot = M-bar^{-1} (R + y(src_t)) (Eq. u_change).
+//   predictor (corr = false): U~ = U^n + h U-dot(V^n) into u_out; V~ is not stored.
+//   corrector (corr = true): V~ = V^n + h grad U^n formed in registers,
+//     V^{n+1} = V^n + h/2 (grad U^n + grad U~) into v_out,
+//     U^{n+1} = (U^n + U~) / 2 + h/2 U-dot(V~) into u_out.
+// V is element-local, [E][2][nq] (element, component, local node). 512 threads, p+1 lanes
+// per element.
 template <typename T>
 struct HeunArgs {
     const int32_t* conn;      // [E][nq]
@@ -116,11 +118,12 @@ struct HeunArgs {
     int64_t E;
     uint32_t conn_bytes, G_bytes, state_bytes;
     const int32_t *tile_eb, *tile_nb, *halo_b, *halo;
-    const T *u_a, *u_base;
+    const T* u0;              // U^n
+    const T* u1;              // U~ (corrector)
     T* u_out;
-    const T *v_a, *v_base;
-    T* v_out;
-    T alpha, beta, gamma;
+    const T* v0;              // V^n
+    T* v_out;                 // V^{n+1} (corrector)
+    T h;
     int32_t lds_own;          // owned-node slots of the LDS prefetch arrays (64-aligned)
     const int32_t *src_b, *src_loc, *src_shot;
     const T* src_w;
@@ -133,7 +136,7 @@ struct HeunArgs {
     T D[(kMaxP + 1) * (kMaxP + 1)];
 };
 template <typename T>
-hipError_t launch_heun_stage(int p, int64_t n_tiles, size_t lds_bytes, const HeunArgs<T>& a,
-                             hipStream_t stream);
+hipError_t launch_heun_stage(int p, bool corr, int64_t n_tiles, size_t lds_bytes,
+                             const HeunArgs<T>& a, hipStream_t stream);
 
 }  // namespace sem

@@ -960,15 +960,23 @@ hipError_t launch_p(int sl, int geo, int64_t nt, size_t lds, const StepArgs<T>& 
 }
 
 // ---------------------------------------------------------------------------------------
-// First-order u-v system, one Heun stage. At GLL point (i, j) of an element the reference
-// derivatives of u give grad u = J^-T (d/dxi, d/deta) u (V-dot, Eq. v_change), and V_a
-// enters R through A_xi = w_i w_j (Vx y_eta - Vy x_eta), A_eta = w_i w_j (Vy x_xi - Vx y_xi)
-// (det J cancels): R(a, b) -= D(i, a) A_xi(i, b) and D(j, b) A_eta(a, j). R is summed into
-// the tile's owned nodes in FP64 LDS words; the owned nodes then take U_out.
-// Row-lane Heun stage: the lane layout of step_rows_kernel (p+1 lanes per element, lane j
-// holds row j, a per-element LDS stage exchanges values across rows within the wave).
-// V is element-major [E][2][nq], so a row's p+1 values of a component are contiguous.
-template <typename T, int P>
+// First-order u-v system with Heun's scheme, one launch per stage. At GLL point (i, j) of an
+// element the reference derivatives of u give grad u = J^-T (d/dxi, d/deta) u (V-dot,
+// Eq. v_change), and V enters R through A_xi = w_i w_j (Vx y_eta - Vy x_eta),
+// A_eta = w_i w_j (Vy x_xi - Vx y_xi) (det J cancels): R(a, b) -= D(i, a) A_xi(i, b) and
+// D(j, b) A_eta(a, j). R is summed into the tile's owned nodes in FP64 LDS words; the owned
+// nodes then take their new U.
+//   predictor (CORR = false): R(V^n); U~ = U^n + h M-bar^-1 (R + y(t_n)). V~ is not stored.
+//   corrector (CORR = true): V~ = V^n + h grad U^n is formed again in registers for every
+//     element the tile touches (its flux needs it); own elements write
+//     V^{n+1} = V^n + h/2 (grad U^n + grad U~); R(V~);
+//     U^{n+1} = U^n / 2 + U~ / 2 + h/2 M-bar^-1 (R + y(t_{n+1})).
+// Forming V~ again costs the corrector a second gather of U, and saves writing V~ and reading
+// it back (4 of the 10 element-local V words per local node and step).
+// Lane layout of step_rows_kernel: p+1 lanes per element, lane j holds row j, a per-element
+// LDS stage exchanges values across rows within the wave. V is element-major [E][2][nq], so
+// a row's p+1 values of a component are contiguous.
+template <typename T, int P, bool CORR>
 __global__ void __launch_bounds__(kRowBlock / 2) heun_rows_kernel(const HeunArgs<T> a) {
     constexpr int RB = kRowBlock / 2;                  // 512 threads
     constexpr int N = P + 1, NQ = N * N;
@@ -978,12 +986,12 @@ __global__ void __launch_bounds__(kRowBlock / 2) heun_rows_kernel(const HeunArgs
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* stage = reinterpret_cast<T*>(smem_raw);          // [EPB][NQP]
     double* acc = reinterpret_cast<double*>(stage + EPB * NQP);   // [owned nodes]
-    // U_base, U_a and 1/M-bar of the owned nodes, prefetched for the update: [3][lds_own]
-    // (FP32 only: in FP64 the 24 bytes per node would halve the blocks resident per CU)
+    // U^n, U~ (corrector) and 1/M-bar of the owned nodes, staged for the update: [3][lds_own]
+    // (FP32 only: in FP64 the extra LDS would halve the blocks resident per CU)
     constexpr bool PRE = sizeof(T) == 4;
-    T* pre_b = reinterpret_cast<T*>(acc + a.lds_own);
-    T* pre_a = pre_b + a.lds_own;
-    T* pre_m = pre_a + a.lds_own;
+    T* pre_0 = reinterpret_cast<T*>(acc + a.lds_own);
+    T* pre_1 = pre_0 + a.lds_own;
+    T* pre_m = pre_1 + a.lds_own;
     const int tile = xcd_logical_block();
     const int nb = a.tile_nb[tile];
     const int nown = a.tile_nb[tile + 1] - nb;
@@ -993,14 +1001,13 @@ __global__ void __launch_bounds__(kRowBlock / 2) heun_rows_kernel(const HeunArgs
     const int n_items = n_own_el + (a.halo_b[tile + 1] - hb);
     const rsrc_t r_conn = make_rsrc(a.conn, a.conn_bytes);
     const rsrc_t r_G = make_rsrc(a.G, a.G_bytes);
-    const rsrc_t r_u = make_rsrc(a.u_a, a.state_bytes);
-    const bool same_base = a.v_base == a.v_a;
-    const bool same_u = a.u_base == a.u_a;             // predictor: U_base is U_a
+    const rsrc_t r_u0 = make_rsrc(a.u0, a.state_bytes);
+    const rsrc_t r_u1 = make_rsrc(CORR ? a.u1 : a.u0, a.state_bytes);
     if constexpr (PRE) {
         const int ndw = nown * (int)(sizeof(T) / 4);
         const uint32_t off = (uint32_t)nb * (uint32_t)sizeof(T);
-        if (!same_u) lds_prefetch<RB>(make_rsrc(a.u_base, a.state_bytes), off, pre_b, ndw);
-        lds_prefetch<RB>(r_u, off, pre_a, ndw);
+        lds_prefetch<RB>(r_u0, off, pre_0, ndw);
+        if constexpr (CORR) lds_prefetch<RB>(r_u1, off, pre_1, ndw);
         lds_prefetch<RB>(make_rsrc(a.minv_w, a.state_bytes), off, pre_m, ndw);
     }
     for (int i = threadIdx.x; i < nown; i += RB) acc[i] = 0.0;
@@ -1016,6 +1023,7 @@ __global__ void __launch_bounds__(kRowBlock / 2) heun_rows_kernel(const HeunArgs
             xij = a.xi[jj];
             wj = a.w[jj];
         }
+    const T h = a.h, hh = T(0.5) * a.h;
     for (int base = 0; base < n_items; base += EPB) {
         const int k = base + slot;
         if (kw >= EPW || k >= n_items) continue;
@@ -1025,39 +1033,63 @@ __global__ void __launch_bounds__(kRowBlock / 2) heun_rows_kernel(const HeunArgs
         load_ids<N>(r_conn, (uint32_t)(e * NQ + N * j) * 4u, idx);
         T bl[8];
         load_rec8(r_G, (uint32_t)e * 8u * (uint32_t)sizeof(T), bl);
-        T u[N], vx[N], vy[N];
+        T vx[N], vy[N];
         const int64_t vrow = (int64_t)e * 2 * NQ + N * j;   // component 0 of row j
 #pragma unroll
         for (int i = 0; i < N; ++i) {
-            u[i] = bload<T>(r_u, (uint32_t)idx[i] * (uint32_t)sizeof(T));
-            vx[i] = a.v_a[vrow + i];
-            vy[i] = a.v_a[vrow + NQ + i];
+            vx[i] = a.v0[vrow + i];
+            vy[i] = a.v0[vrow + NQ + i];
         }
-#pragma unroll
-        for (int i = 0; i < N; ++i) st[i + N * j] = u[i];
         // x_xi, y_xi at eta = xi_j are constant along the row; x_eta, y_eta depend on xi_i
         const T xs = bl[0] + bl[2] * xij, ys = bl[3] + bl[5] * xij;
+        if constexpr (CORR) {
+            // grad u at (i, j) from this lane's row u[] and the other rows in the stage
+            auto grad = [&](const T (&u)[N], int i, T& dx, T& dy) {
+                const T xt = bl[1] + bl[2] * a.xi[i], yt = bl[4] + bl[5] * a.xi[i];
+                T gxi = T(0), geta = T(0);
+#pragma unroll
+                for (int m = 0; m < N; ++m) {
+                    gxi += a.D[i * N + m] * u[m];
+                    geta += a.D[j * N + m] * st[i + N * m];
+                }
+                const T inv = T(1) / (xs * yt - xt * ys);
+                dx = (yt * gxi - ys * geta) * inv;
+                dy = (xs * geta - xt * gxi) * inv;
+            };
+            T u[N], nx[N], ny[N];
+#pragma unroll
+            for (int i = 0; i < N; ++i) u[i] = bload<T>(r_u0, (uint32_t)idx[i] * (uint32_t)sizeof(T));
+#pragma unroll
+            for (int i = 0; i < N; ++i) st[i + N * j] = u[i];
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                T dx, dy;
+                grad(u, i, dx, dy);
+                nx[i] = vx[i] + hh * dx;
+                ny[i] = vy[i] + hh * dy;
+                vx[i] += h * dx;                       // V~
+                vy[i] += h * dy;
+            }
+            if (own) {
+#pragma unroll
+                for (int i = 0; i < N; ++i) u[i] = bload<T>(r_u1, (uint32_t)idx[i] * (uint32_t)sizeof(T));
+#pragma unroll
+                for (int i = 0; i < N; ++i) st[i + N * j] = u[i];
+#pragma unroll
+                for (int i = 0; i < N; ++i) {
+                    T dx, dy;
+                    grad(u, i, dx, dy);
+                    a.v_out[vrow + i] = nx[i] + hh * dx;
+                    a.v_out[vrow + NQ + i] = ny[i] + hh * dy;
+                }
+            }
+        }
         T r[N], aeta[N];
 #pragma unroll
         for (int aa = 0; aa < N; ++aa) r[aa] = T(0);
 #pragma unroll
         for (int i = 0; i < N; ++i) {
             const T xt = bl[1] + bl[2] * a.xi[i], yt = bl[4] + bl[5] * a.xi[i];
-            T gxi = T(0), geta = T(0);
-#pragma unroll
-            for (int m = 0; m < N; ++m) {
-                gxi += a.D[i * N + m] * u[m];
-                geta += a.D[j * N + m] * st[i + N * m];
-            }
-            const T inv = T(1) / (xs * yt - xt * ys);
-            const T dudx = (yt * gxi - ys * geta) * inv;
-            const T dudy = (xs * geta - xt * gxi) * inv;
-            if (own) {
-                const T bx = same_base ? vx[i] : a.v_base[vrow + i];
-                const T by = same_base ? vy[i] : a.v_base[vrow + NQ + i];
-                a.v_out[vrow + i] = a.alpha * bx + a.beta * vx[i] + a.gamma * dudx;
-                a.v_out[vrow + NQ + i] = a.alpha * by + a.beta * vy[i] + a.gamma * dudy;
-            }
             const T wij = a.w[i] * wj;
             const T axi = wij * (vx[i] * yt - vy[i] * xt);
             aeta[i] = wij * (vy[i] * xs - vx[i] * ys);
@@ -1097,17 +1129,17 @@ __global__ void __launch_bounds__(kRowBlock / 2) heun_rows_kernel(const HeunArgs
     }
     for (int i = threadIdx.x; i < nown; i += RB) {
         const int node = nb + i;
-        T ua, ub, mi;
+        T u0, u1, mi;
         if constexpr (PRE) {
-            ua = pre_a[i];
-            ub = same_u ? ua : pre_b[i];
+            u0 = pre_0[i];
+            u1 = CORR ? pre_1[i] : u0;
             mi = pre_m[i];
         } else {
-            ua = a.u_a[node];
-            ub = same_u ? ua : a.u_base[node];
+            u0 = a.u0[node];
+            u1 = CORR ? a.u1[node] : u0;
             mi = a.minv_w[node];
         }
-        const T un = a.alpha * ub + a.beta * ua + a.gamma * (mi * (T)acc[i]);
+        const T un = CORR ? T(0.5) * u0 + T(0.5) * u1 + hh * (mi * (T)acc[i]) : u0 + h * (mi * (T)acc[i]);
         a.u_out[node] = un;
         acc[i] = (double)un;
     }
@@ -1122,9 +1154,9 @@ __global__ void __launch_bounds__(kRowBlock / 2) heun_rows_kernel(const HeunArgs
 }
 
 template <typename T, int P>
-hipError_t launch_heun_p(int64_t n_tiles, size_t lds, const HeunArgs<T>& a, hipStream_t st) {
+hipError_t launch_heun_p(bool corr, int64_t n_tiles, size_t lds, const HeunArgs<T>& a, hipStream_t st) {
     constexpr int N = P + 1, NQP = (N * N + 3) & ~3, RB = kRowBlock / 2, EPB = (64 / N) * (RB / 64);
-    auto fn = heun_rows_kernel<T, P>;
+    auto fn = corr ? heun_rows_kernel<T, P, true> : heun_rows_kernel<T, P, false>;
     // stage, accumulator and (FP32) the three prefetch arrays
     lds = (size_t)EPB * NQP * sizeof(T) + (size_t)a.lds_own * sizeof(double) +
           (sizeof(T) == 4 ? (size_t)3 * a.lds_own * sizeof(T) : 0);
@@ -1265,15 +1297,16 @@ hipError_t launch_grad_to_original(const double* acc, double* out, const int32_t
 }
 
 template <typename T>
-hipError_t launch_heun_stage(int p, int64_t nt, size_t lds, const HeunArgs<T>& a, hipStream_t st) {
+hipError_t launch_heun_stage(int p, bool corr, int64_t nt, size_t lds, const HeunArgs<T>& a,
+                             hipStream_t st) {
     switch (p) {
-        case 1: return launch_heun_p<T, 1>(nt, lds, a, st);
-        case 2: return launch_heun_p<T, 2>(nt, lds, a, st);
-        case 3: return launch_heun_p<T, 3>(nt, lds, a, st);
-        case 4: return launch_heun_p<T, 4>(nt, lds, a, st);
-        case 5: return launch_heun_p<T, 5>(nt, lds, a, st);
-        case 6: return launch_heun_p<T, 6>(nt, lds, a, st);
-        case 7: return launch_heun_p<T, 7>(nt, lds, a, st);
+        case 1: return launch_heun_p<T, 1>(corr, nt, lds, a, st);
+        case 2: return launch_heun_p<T, 2>(corr, nt, lds, a, st);
+        case 3: return launch_heun_p<T, 3>(corr, nt, lds, a, st);
+        case 4: return launch_heun_p<T, 4>(corr, nt, lds, a, st);
+        case 5: return launch_heun_p<T, 5>(corr, nt, lds, a, st);
+        case 6: return launch_heun_p<T, 6>(corr, nt, lds, a, st);
+        case 7: return launch_heun_p<T, 7>(corr, nt, lds, a, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -1287,7 +1320,7 @@ hipError_t launch_heun_stage(int p, int64_t nt, size_t lds, const HeunArgs<T>& a
     template hipError_t launch_fill<T>(T*, T, int64_t, hipStream_t);                              \
     template hipError_t launch_scale<T>(T*, double, int64_t, hipStream_t);                        \
     template hipError_t launch_sumsq<T>(const T*, int64_t, double*, hipStream_t);                 \
-    template hipError_t launch_heun_stage<T>(int, int64_t, size_t, const HeunArgs<T>&, hipStream_t);
+    template hipError_t launch_heun_stage<T>(int, bool, int64_t, size_t, const HeunArgs<T>&, hipStream_t);
 
 SEM_INSTANTIATE(float)
 SEM_INSTANTIATE(double)
