@@ -54,6 +54,10 @@ struct sem_ctx {
     // the end of a step ([E][2][nq] each), and 1 / M-bar weighted by 1/c^2
     int formulation = SEM_FORM_LEAPFROG;
     DevBuf u_next, hv[2], minv_w;
+    // the next step's predicted U~ (written by the fused corrector) and whether u[cur ^ 1]
+    // holds U~ for the current state (false after any change of state or sources)
+    DevBuf u_pred;
+    bool heun_pred_valid = false;
     std::vector<DevBuf> extra;        // scratch owned by the adjoint driver
 };
 
@@ -181,8 +185,10 @@ int launch(sem_ctx* c, const sem::StepArgs<T>& a) {
     return SEM_OK;
 }
 
-// One Heun step of the first-order system: predictor (U, V) -> U~ in u[cur^1]; corrector
-// from U~ and (U, V) into u_next, hv[1]; then those become the state.
+// One Heun step of the first-order system: predictor (U, V) -> U~ in u[cur^1], only when
+// u[cur^1] does not hold it yet (first step, or after a change of state or sources); then
+// the corrector from U~ and (U, V) into u_next, hv[1], fused with the next step's predictor
+// into u_pred; those become the state, and u[cur^1] holds the next U~.
 template <typename T>
 int heun_step(sem_ctx* c, T* trace, int64_t cols, int64_t col) {
     const sem::Plan& P = c->plan;
@@ -216,17 +222,20 @@ int heun_step(sem_ctx* c, T* trace, int64_t cols, int64_t col) {
     const int64_t nt = (int64_t)P.tile_eb.size() - 1;
     const size_t lds = (size_t)P.max_owned * sizeof(double);
     const T h = (T)P.dt;
-    // predictor
     a.u0 = (const T*)c->u[c->cur].p;
-    a.u_out = (T*)c->u[c->cur ^ 1].p;
     a.v0 = (const T*)c->hv[0].p;
     a.h = h;
-    a.src_t = (double)c->step * P.dt;
-    SEM_HIP(c, sem::launch_heun_stage<T>(P.p, false, nt, lds, a, c->stream));
-    // corrector
+    if (!c->heun_pred_valid) {
+        // predictor: U~ into u[cur ^ 1]
+        a.u_out = (T*)c->u[c->cur ^ 1].p;
+        a.src_t = (double)c->step * P.dt;
+        SEM_HIP(c, sem::launch_heun_stage<T>(P.p, 0, nt, lds, a, c->stream));
+    }
+    // corrector, fused with the next step's predictor
     a.u1 = (const T*)c->u[c->cur ^ 1].p;
     a.u_out = (T*)c->u_next.p;
     a.v_out = (T*)c->hv[1].p;
+    a.u_pred = (T*)c->u_pred.p;
     a.src_t = (double)(c->step + 1) * P.dt;
     if (trace && c->n_rec > 0) {
         a.rec_b = (const int32_t*)c->rec_b.p;
@@ -236,9 +245,11 @@ int heun_step(sem_ctx* c, T* trace, int64_t cols, int64_t col) {
         a.trace_cols = cols;
         a.trace_col = col;
     }
-    SEM_HIP(c, sem::launch_heun_stage<T>(P.p, true, nt, lds, a, c->stream));
+    SEM_HIP(c, sem::launch_heun_stage<T>(P.p, 2, nt, lds, a, c->stream));
     std::swap(c->u[c->cur], c->u_next);
+    std::swap(c->u[c->cur ^ 1], c->u_pred);
     std::swap(c->hv[0], c->hv[1]);
+    c->heun_pred_valid = true;
     c->step += 1;
     return SEM_OK;
 }
@@ -286,6 +297,7 @@ int zero_state(sem_ctx* c) {
     }
     c->cur = 0;
     c->step = 0;
+    c->heun_pred_valid = false;
     return SEM_OK;
 }
 
@@ -465,6 +477,7 @@ int setup_heun(sem_ctx* c) {
     const size_t nvq = (size_t)2 * nq * P.ne * sizeof(T);
     for (int k = 0; k < 2; ++k) SEM_HIP(c, dev_alloc(c->hv[k], nvq));
     SEM_HIP(c, dev_alloc(c->u_next, (size_t)P.nn * sizeof(T)));
+    SEM_HIP(c, dev_alloc(c->u_pred, (size_t)P.nn * sizeof(T)));
     return zero_state<T>(c);
 }
 
@@ -920,11 +933,11 @@ int sem_get_info(const sem_ctx* c, sem_info* info) {
     info->alg_flops_per_step = (double)P.ne * c->S * (8.0 * n * n * n + 7.0 * n * n) +
                                (double)P.nn * c->S * 4.0;
     if (c->formulation == SEM_FORM_HEUN) {
-        // two stages; per element: ids and the 8-word record each stage, V^n read twice and
-        // V^{n+1} written once (2 nq words each); per node: U^n read twice, U~ written and
-        // read, U^{n+1} written, 1/M-bar read twice
-        info->alg_bytes_per_step = (double)P.ne * (2.0 * (nq * 4.0 + 8.0 * w) + 3.0 * 2.0 * nq * w) +
-                                   (double)P.nn * 7.0 * w;
+        // one launch per step (the corrector fused with the next predictor); per element:
+        // ids and the 8-word record, V^n read and V^{n+1} written (2 nq words each); per
+        // node: U^n and U~ read, U^{n+1} and the next U~ written, 1/M-bar read
+        info->alg_bytes_per_step = (double)P.ne * (nq * 4.0 + 8.0 * w + 2.0 * 2.0 * nq * w) +
+                                   (double)P.nn * 5.0 * w;
         info->kernel_bytes_per_step = info->alg_bytes_per_step;
         info->alg_flops_per_step *= 2.0;
     }
@@ -958,6 +971,7 @@ int sem_set_sources(sem_ctx* c, int32_t n, const double* xy, const int32_t* shot
     c->f0 = f0;
     c->t0 = t0;
     if (!c->host_only) { int rc = set_device(c); if (rc) return rc; }
+    c->heun_pred_valid = false;
     return c->precision == SEM_F64 ? set_sources_t<double>(c, n, xy, shot, node_out)
                                    : set_sources_t<float>(c, n, xy, shot, node_out);
 }
@@ -1043,6 +1057,7 @@ int sem_set_field(sem_ctx* c, int32_t which, const void* dev) {
     rc = set_device(c);
     if (rc) return rc;
     void* dst = which == SEM_FIELD_U ? c->u[c->cur].p : c->v.p;
+    c->heun_pred_valid = false;
     if (c->precision == SEM_F64)
         SEM_HIP(c, sem::launch_nodes_from_original<double>((const double*)dev, (double*)dst,
                                                            (const int32_t*)c->n2o_node.p, c->plan.nn, c->S, row_kernel(c),
@@ -1198,7 +1213,7 @@ void sem_destroy(sem_ctx* c) {
         DevBuf* bufs[] = {&c->conn, &c->G, &c->c2, &c->dtminv, &c->tile_eb, &c->tile_nb, &c->tile_ns, &c->halo_b,
                           &c->halo, &c->n2o_node, &c->n2o_elem, &c->u[0], &c->u[1], &c->v,
                           &c->src_b, &c->src_loc, &c->src_shot, &c->src_w, &c->rec_b, &c->rec_loc,
-                          &c->rec_idx, &c->u_next, &c->hv[0], &c->hv[1], &c->minv_w};
+                          &c->rec_idx, &c->u_next, &c->hv[0], &c->hv[1], &c->minv_w, &c->u_pred};
         for (DevBuf* b : bufs) dev_free(*b);
     }
     delete c;

@@ -104,10 +104,12 @@ hipError_t launch_grad_to_original(const double* acc, double* out, const int32_t
 // shot, tiles, halo and record layout of the single-shot kernel. V-dot = grad u at the local
 // nodes of an element (Eq. v_change, F = I); R = -sum w detJ V . grad N (Eq. u_change_r_effic,
 // B = -I) summed into the owned nodes; U-dot = M-bar^{-1} (R + y(src_t)) (Eq. u_change).
-//   predictor (corr = false): U~ = U^n + h U-dot(V^n) into u_out; V~ is not stored.
-//   corrector (corr = true): V~ = V^n + h grad U^n formed in registers,
+//   predictor (mode 0): U~ = U^n + h U-dot(V^n) into u_out; V~ is not stored.
+//   corrector (mode 1): V~ = V^n + h grad U^n formed in registers,
 //     V^{n+1} = V^n + h/2 (grad U^n + grad U~) into v_out,
 //     U^{n+1} = (U^n + U~) / 2 + h/2 U-dot(V~) into u_out.
+//   fused corrector (mode 2): the corrector, and the next step's predictor
+//     U~ = U^{n+1} + h U-dot(V^{n+1}) into u_pred (V^{n+1} formed for halo elements too).
 // V is element-local, [E][2][nq] (element, component, local node). 512 threads, p+1 lanes
 // per element.
 template <typename T>
@@ -123,6 +125,7 @@ struct HeunArgs {
     T* u_out;
     const T* v0;              // V^n
     T* v_out;                 // V^{n+1} (corrector)
+    T* u_pred;                // fused corrector: the next step's U~
     T h;
     int32_t lds_own;          // owned-node slots of the LDS prefetch arrays (64-aligned)
     const int32_t *src_b, *src_loc, *src_shot;
@@ -136,7 +139,7 @@ struct HeunArgs {
     T D[(kMaxP + 1) * (kMaxP + 1)];
 };
 template <typename T>
-hipError_t launch_heun_stage(int p, bool corr, int64_t n_tiles, size_t lds_bytes,
+hipError_t launch_heun_stage(int p, int mode, int64_t n_tiles, size_t lds_bytes,
                              const HeunArgs<T>& a, hipStream_t stream);
 
 }  // namespace sem

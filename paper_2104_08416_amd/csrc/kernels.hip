@@ -971,12 +971,16 @@ hipError_t launch_p(int sl, int geo, int64_t nt, size_t lds, const StepArgs<T>& 
 //     element the tile touches (its flux needs it); own elements write
 //     V^{n+1} = V^n + h/2 (grad U^n + grad U~); R(V~);
 //     U^{n+1} = U^n / 2 + U~ / 2 + h/2 M-bar^-1 (R + y(t_{n+1})).
+//   FUSE (with CORR): also the next step's predictor. V^{n+1} is formed for the halo
+//     elements too (U^n, U~ and V^n are complete before the launch), R(V^{n+1}) goes into a
+//     second accumulator, and the owned nodes also take the next
+//     U~ = U^{n+1} + h M-bar^-1 (R(V^{n+1}) + y(t_{n+1})) into u_pred: one launch per step.
 // Forming V~ again costs the corrector a second gather of U, and saves writing V~ and reading
 // it back (4 of the 10 element-local V words per local node and step).
 // Lane layout of step_rows_kernel: p+1 lanes per element, lane j holds row j, a per-element
 // LDS stage exchanges values across rows within the wave. V is element-major [E][2][nq], so
 // a row's p+1 values of a component are contiguous.
-template <typename T, int P, bool CORR>
+template <typename T, int P, bool CORR, bool FUSE>
 __global__ void __launch_bounds__(kRowBlock / 2) heun_rows_kernel(const HeunArgs<T> a) {
     constexpr int RB = kRowBlock / 2;                  // 512 threads
     constexpr int N = P + 1, NQ = N * N;
@@ -986,10 +990,12 @@ __global__ void __launch_bounds__(kRowBlock / 2) heun_rows_kernel(const HeunArgs
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* stage = reinterpret_cast<T*>(smem_raw);          // [EPB][NQP]
     double* acc = reinterpret_cast<double*>(stage + EPB * NQP);   // [owned nodes]
+    // FUSE: R(V^{n+1}) of the next step's predictor, [owned nodes]
+    double* acc2 = acc + a.lds_own;
     // U^n, U~ (corrector) and 1/M-bar of the owned nodes, staged for the update: [3][lds_own]
     // (FP32 only: in FP64 the extra LDS would halve the blocks resident per CU)
     constexpr bool PRE = sizeof(T) == 4;
-    T* pre_0 = reinterpret_cast<T*>(acc + a.lds_own);
+    T* pre_0 = reinterpret_cast<T*>(acc + (FUSE ? 2 : 1) * a.lds_own);
     T* pre_1 = pre_0 + a.lds_own;
     T* pre_m = pre_1 + a.lds_own;
     const int tile = xcd_logical_block();
@@ -1010,7 +1016,10 @@ __global__ void __launch_bounds__(kRowBlock / 2) heun_rows_kernel(const HeunArgs
         if constexpr (CORR) lds_prefetch<RB>(r_u1, off, pre_1, ndw);
         lds_prefetch<RB>(make_rsrc(a.minv_w, a.state_bytes), off, pre_m, ndw);
     }
-    for (int i = threadIdx.x; i < nown; i += RB) acc[i] = 0.0;
+    for (int i = threadIdx.x; i < nown; i += RB) {
+        acc[i] = 0.0;
+        if constexpr (FUSE) acc2[i] = 0.0;
+    }
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int kw = lane / N, j = lane - kw * N;
@@ -1042,6 +1051,40 @@ __global__ void __launch_bounds__(kRowBlock / 2) heun_rows_kernel(const HeunArgs
         }
         // x_xi, y_xi at eta = xi_j are constant along the row; x_eta, y_eta depend on xi_i
         const T xs = bl[0] + bl[2] * xij, ys = bl[3] + bl[5] * xij;
+        // R of the flux of (fx, fy) for this lane's row, summed into the accumulator A
+        auto flux = [&](const T (&fx)[N], const T (&fy)[N], double* A) {
+            T r[N], aeta[N];
+#pragma unroll
+            for (int aa = 0; aa < N; ++aa) r[aa] = T(0);
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                const T xt = bl[1] + bl[2] * a.xi[i], yt = bl[4] + bl[5] * a.xi[i];
+                const T wij = a.w[i] * wj;
+                const T axi = wij * (fx[i] * yt - fy[i] * xt);
+                aeta[i] = wij * (fy[i] * xs - fx[i] * ys);
+                // along the row: R(aa, j) -= D(i, aa) A_xi(i, j)
+#pragma unroll
+                for (int aa = 0; aa < N; ++aa) r[aa] -= a.D[i * N + aa] * axi;
+            }
+            // across rows: R(aa, j) -= sum_m D(m, j) A_eta(aa, m), A_eta exchanged via the stage
+#pragma unroll
+            for (int i = 0; i < N; ++i) st[i + N * j] = aeta[i];
+#pragma unroll
+            for (int m = 0; m < N; ++m) {
+                const T dmj = a.D[m * N + j];
+#pragma unroll
+                for (int aa = 0; aa < N; ++aa) r[aa] -= dmj * st[aa + N * m];
+            }
+            const bool inner_row = j > 0 && j < P;
+#pragma unroll
+            for (int aa = 0; aa < N; ++aa) {
+                const int loc = idx[aa] - nb;
+                if ((unsigned)loc < (unsigned)nown) {
+                    if (aa > 0 && aa < P && inner_row) A[loc] = (double)r[aa];
+                    else atomicAdd(&A[loc], (double)r[aa]);
+                }
+            }
+        };
         if constexpr (CORR) {
             // grad u at (i, j) from this lane's row u[] and the other rows in the stage
             auto grad = [&](const T (&u)[N], int i, T& dx, T& dy) {
@@ -1070,7 +1113,7 @@ __global__ void __launch_bounds__(kRowBlock / 2) heun_rows_kernel(const HeunArgs
                 vx[i] += h * dx;                       // V~
                 vy[i] += h * dy;
             }
-            if (own) {
+            if (FUSE || own) {
 #pragma unroll
                 for (int i = 0; i < N; ++i) u[i] = bload<T>(r_u1, (uint32_t)idx[i] * (uint32_t)sizeof(T));
 #pragma unroll
@@ -1079,42 +1122,17 @@ __global__ void __launch_bounds__(kRowBlock / 2) heun_rows_kernel(const HeunArgs
                 for (int i = 0; i < N; ++i) {
                     T dx, dy;
                     grad(u, i, dx, dy);
-                    a.v_out[vrow + i] = nx[i] + hh * dx;
-                    a.v_out[vrow + NQ + i] = ny[i] + hh * dy;
+                    nx[i] += hh * dx;                  // V^{n+1}
+                    ny[i] += hh * dy;
+                    if (own) {
+                        a.v_out[vrow + i] = nx[i];
+                        a.v_out[vrow + NQ + i] = ny[i];
+                    }
                 }
             }
+            if constexpr (FUSE) flux(nx, ny, acc2);
         }
-        T r[N], aeta[N];
-#pragma unroll
-        for (int aa = 0; aa < N; ++aa) r[aa] = T(0);
-#pragma unroll
-        for (int i = 0; i < N; ++i) {
-            const T xt = bl[1] + bl[2] * a.xi[i], yt = bl[4] + bl[5] * a.xi[i];
-            const T wij = a.w[i] * wj;
-            const T axi = wij * (vx[i] * yt - vy[i] * xt);
-            aeta[i] = wij * (vy[i] * xs - vx[i] * ys);
-            // along the row: R(aa, j) -= D(i, aa) A_xi(i, j)
-#pragma unroll
-            for (int aa = 0; aa < N; ++aa) r[aa] -= a.D[i * N + aa] * axi;
-        }
-        // across rows: R(aa, j) -= sum_m D(m, j) A_eta(aa, m), A_eta exchanged via the stage
-#pragma unroll
-        for (int i = 0; i < N; ++i) st[i + N * j] = aeta[i];
-#pragma unroll
-        for (int m = 0; m < N; ++m) {
-            const T dmj = a.D[m * N + j];
-#pragma unroll
-            for (int aa = 0; aa < N; ++aa) r[aa] -= dmj * st[aa + N * m];
-        }
-        const bool inner_row = j > 0 && j < P;
-#pragma unroll
-        for (int aa = 0; aa < N; ++aa) {
-            const int loc = idx[aa] - nb;
-            if ((unsigned)loc < (unsigned)nown) {
-                if (aa > 0 && aa < P && inner_row) acc[loc] = (double)r[aa];
-                else atomicAdd(&acc[loc], (double)r[aa]);
-            }
-        }
+        flux(vx, vy, acc);
     }
     __builtin_amdgcn_s_waitcnt(0);                     // this wave's LDS prefetches landed
     __syncthreads();
@@ -1123,7 +1141,10 @@ __global__ void __launch_bounds__(kRowBlock / 2) heun_rows_kernel(const HeunArgs
         if (se > sb) {
             const T amp = (T)ricker(a.src_t, a.f0, a.t0);
             for (int i = sb + threadIdx.x; i < se; i += RB)
-                if (a.src_shot[i] == 0) atomicAdd(&acc[a.src_loc[i]], (double)(a.src_w[i] * amp));
+                if (a.src_shot[i] == 0) {
+                    atomicAdd(&acc[a.src_loc[i]], (double)(a.src_w[i] * amp));
+                    if constexpr (FUSE) atomicAdd(&acc2[a.src_loc[i]], (double)(a.src_w[i] * amp));
+                }
             __syncthreads();
         }
     }
@@ -1141,6 +1162,7 @@ __global__ void __launch_bounds__(kRowBlock / 2) heun_rows_kernel(const HeunArgs
         }
         const T un = CORR ? T(0.5) * u0 + T(0.5) * u1 + hh * (mi * (T)acc[i]) : u0 + h * (mi * (T)acc[i]);
         a.u_out[node] = un;
+        if constexpr (FUSE) a.u_pred[node] = un + h * (mi * (T)acc2[i]);   // next step's U~
         acc[i] = (double)un;
     }
     if (a.trace != nullptr) {
@@ -1154,11 +1176,12 @@ __global__ void __launch_bounds__(kRowBlock / 2) heun_rows_kernel(const HeunArgs
 }
 
 template <typename T, int P>
-hipError_t launch_heun_p(bool corr, int64_t n_tiles, size_t lds, const HeunArgs<T>& a, hipStream_t st) {
+hipError_t launch_heun_p(int mode, int64_t n_tiles, size_t lds, const HeunArgs<T>& a, hipStream_t st) {
     constexpr int N = P + 1, NQP = (N * N + 3) & ~3, RB = kRowBlock / 2, EPB = (64 / N) * (RB / 64);
-    auto fn = corr ? heun_rows_kernel<T, P, true> : heun_rows_kernel<T, P, false>;
-    // stage, accumulator and (FP32) the three prefetch arrays
-    lds = (size_t)EPB * NQP * sizeof(T) + (size_t)a.lds_own * sizeof(double) +
+    auto fn = mode == 2 ? heun_rows_kernel<T, P, true, true>
+              : (mode == 1 ? heun_rows_kernel<T, P, true, false> : heun_rows_kernel<T, P, false, false>);
+    // stage, accumulator(s) and (FP32) the three prefetch arrays
+    lds = (size_t)EPB * NQP * sizeof(T) + (size_t)(mode == 2 ? 2 : 1) * a.lds_own * sizeof(double) +
           (sizeof(T) == 4 ? (size_t)3 * a.lds_own * sizeof(T) : 0);
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
@@ -1297,16 +1320,16 @@ hipError_t launch_grad_to_original(const double* acc, double* out, const int32_t
 }
 
 template <typename T>
-hipError_t launch_heun_stage(int p, bool corr, int64_t nt, size_t lds, const HeunArgs<T>& a,
+hipError_t launch_heun_stage(int p, int mode, int64_t nt, size_t lds, const HeunArgs<T>& a,
                              hipStream_t st) {
     switch (p) {
-        case 1: return launch_heun_p<T, 1>(corr, nt, lds, a, st);
-        case 2: return launch_heun_p<T, 2>(corr, nt, lds, a, st);
-        case 3: return launch_heun_p<T, 3>(corr, nt, lds, a, st);
-        case 4: return launch_heun_p<T, 4>(corr, nt, lds, a, st);
-        case 5: return launch_heun_p<T, 5>(corr, nt, lds, a, st);
-        case 6: return launch_heun_p<T, 6>(corr, nt, lds, a, st);
-        case 7: return launch_heun_p<T, 7>(corr, nt, lds, a, st);
+        case 1: return launch_heun_p<T, 1>(mode, nt, lds, a, st);
+        case 2: return launch_heun_p<T, 2>(mode, nt, lds, a, st);
+        case 3: return launch_heun_p<T, 3>(mode, nt, lds, a, st);
+        case 4: return launch_heun_p<T, 4>(mode, nt, lds, a, st);
+        case 5: return launch_heun_p<T, 5>(mode, nt, lds, a, st);
+        case 6: return launch_heun_p<T, 6>(mode, nt, lds, a, st);
+        case 7: return launch_heun_p<T, 7>(mode, nt, lds, a, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -1320,7 +1343,7 @@ hipError_t launch_heun_stage(int p, bool corr, int64_t nt, size_t lds, const Heu
     template hipError_t launch_fill<T>(T*, T, int64_t, hipStream_t);                              \
     template hipError_t launch_scale<T>(T*, double, int64_t, hipStream_t);                        \
     template hipError_t launch_sumsq<T>(const T*, int64_t, double*, hipStream_t);                 \
-    template hipError_t launch_heun_stage<T>(int, bool, int64_t, size_t, const HeunArgs<T>&, hipStream_t);
+    template hipError_t launch_heun_stage<T>(int, int, int64_t, size_t, const HeunArgs<T>&, hipStream_t);
 
 SEM_INSTANTIATE(float)
 SEM_INSTANTIATE(double)

@@ -309,3 +309,35 @@ def test_heun_first_order_matches_oracle(semlib, gpu_ok, prec, tol, nsteps):
     say("heun", prec, "rel L2", err)
     assert err <= tol
     assert rel(tr, tr_o) <= tol
+
+
+def test_heun_state_changes(semlib, gpu_ok):
+    """The Heun path keeps the next step's predicted U between calls; runs split over calls,
+    reset, and a field written between runs (which must discard that prediction) all match
+    the FP64 oracle."""
+    from oracle import first_order
+    say("case heun state changes")
+    wl = workloads.workload("layered1024", n=12)
+    fo = first_order.FirstOrderSEM(wl.vxy, wl.quads, wl.c2, wl.p)
+    s = semlib.Simulator(wl.vxy, wl.quads, wl.c2, wl.p, precision="f64", formulation="heun")
+    xy = fo.node_xy                              # original node numbering, as the fields
+    u0 = np.exp(-((xy[:, 0] - 5000.0) ** 2 + (xy[:, 1] - 4000.0) ** 2) / (2 * 800.0 ** 2))
+    import torch
+    dev = torch.device("cuda")
+    s.set_field(semlib.FIELD_U, torch.tensor(u0[None, :], dtype=torch.float64, device=dev))
+    s.run(20, record=False)
+    s.run(30, record=False)                      # split: 50 steps over two calls
+    u50 = s.get_field(semlib.FIELD_U).double().cpu().numpy()[0]
+    _, u50_o, v50_o = fo.run(50, s.dt, u0=u0)
+    assert rel(u50, u50_o[:, 0]) <= 1e-12
+    u_new = 2.0 * u50                            # a new field with V kept
+    s.set_field(semlib.FIELD_U, torch.tensor(u_new[None, :], dtype=torch.float64, device=dev))
+    s.run(40, record=False)
+    u90 = s.get_field(semlib.FIELD_U).double().cpu().numpy()[0]
+    _, u90_o, _ = fo.run(40, s.dt, u0=u_new, v0=v50_o)
+    assert rel(u90, u90_o[:, 0]) <= 1e-12
+    s.reset()                                    # zero state, then the same 50 steps again
+    s.set_field(semlib.FIELD_U, torch.tensor(u0[None, :], dtype=torch.float64, device=dev))
+    s.run(50, record=False)
+    assert rel(s.get_field(semlib.FIELD_U).double().cpu().numpy()[0], u50_o[:, 0]) <= 1e-12
+    s.close()
