@@ -63,7 +63,9 @@ enum sem_field { SEM_FIELD_U = 0, SEM_FIELD_V = 1 };
  * (1/c^2) u_t = div v + s, v_t = grad u, v stored per element at its GLL nodes, lumped
  * mass weighted by 1/c^2, Heun predictor-corrector (two operator evaluations per step).
  * Single shot only; sources enter as y(t) in the u equation; no adjoint; SEM_FIELD_V is
- * not available (v is element-local). */
+ * not available (v is element-local). Each step's launch also computes the next step's
+ * predictor, kept in the context; sem_reset, sem_set_field and sem_set_sources drop it,
+ * so the next step recomputes it. */
 enum sem_formulation { SEM_FORM_LEAPFROG = 0, SEM_FORM_HEUN = 1 };
 
 /* Input mesh (host arrays, original numbering). */
