@@ -124,7 +124,10 @@ typedef struct {
     double lambda_max;
     double alg_bytes_per_step;  /* algorithmic HBM bytes of one step: per element nq   *
                                  * int32 ids, 3 nq geometric factors and c2; per node *
-                                 * dt/M and, per shot, u and v read and written       */
+                                 * dt/M and, per shot, u and v read and written.      *
+                                 * SEM_FORM_HEUN: per element nq ids, 8 record words, *
+                                 * V read and written (2 nq words each); per node 5   *
+                                 * words (U^n, U~ and 1/M-bar read, two U written)    */
     double alg_flops_per_step;
     double setup_seconds;    /* host setup wall time (numbering, reorder, geometry)   */
     double reorder_seconds;  /* part of setup spent on element and node reordering    */

@@ -185,3 +185,23 @@ def test_walk_orders_on_hand_worked_strip(semlib, kind):
     s.close()
     np.testing.assert_array_equal(e, g[kind]["elements"])
 
+
+
+@pytest.mark.parametrize("prec,w", [("f32", 4), ("f64", 8)])
+def test_algorithmic_bytes_model(semlib, prec, w):
+    """The roofline numerator, from mesh counts alone: leapfrog per element nq int32 ids,
+    3 nq factors and c2, per node dt/M and u, v read and written per shot; the fused Heun
+    step per element ids, the 8-word record, V^n read and V^{n+1} written, per node 5 words."""
+    wl = workloads.workload("layered1024", n=12)
+    nq = (wl.p + 1) ** 2
+    for shots in (1, 64):
+        s = semlib.Simulator(wl.vxy, wl.quads, wl.c2, wl.p, device=-1, precision=prec, n_shots=shots)
+        inf = s.info()
+        E, N = inf["n_elements"], inf["n_nodes"]
+        assert inf["alg_bytes_per_step"] == E * (4 * nq + (3 * nq + 1) * w) + N * w * (1 + 4 * shots)
+        s.close()
+    s = semlib.Simulator(wl.vxy, wl.quads, wl.c2, wl.p, device=-1, precision=prec, formulation="heun")
+    inf = s.info()
+    E, N = inf["n_elements"], inf["n_nodes"]
+    assert inf["alg_bytes_per_step"] == E * (4 * nq + 8 * w + 4 * nq * w) + N * 5 * w
+    s.close()
