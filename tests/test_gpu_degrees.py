@@ -1,8 +1,9 @@
 """GPU parity at every polynomial degree the kernels are built for (p = 1..7), against the
 FP64 CPU oracle: the single-shot row kernel, the 64-shot kernel (one wave per element)
-and the two Heun kernels of the first-order system. The p = 4 cases are covered at larger
-sizes elsewhere; here each degree runs on a small mesh in random element order, so that
-every tile has a large halo, with a source, receivers and the default tiles.
+and the Heun kernels of the first-order system (predictor, fused corrector). The p = 4
+cases are covered at larger sizes elsewhere; here each degree runs on a small mesh in random
+element order, so that every tile has a large halo, with a source, receivers and the
+default tiles.
 
 Tolerances: FP64 rel L2 <= 1e-12 (rounding order only); FP32 rel L2 <= 1e-5; traces: the
 largest error over the largest wavefield value, same bounds.
