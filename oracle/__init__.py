@@ -21,6 +21,8 @@ the Spectral Element Method with Hilbert Space-Filling Curves", 2021):
                   Alg. 3), the CFL time step and the discrete energy.
 * ``adjoint``  -- the discrete adjoint of that recurrence and the gradient of an L2
                   receiver misfit with respect to per-element c^2.
+* ``colour``   -- the greedy element colouring that makes the accumulation of Alg. 2
+                  race-free (Sec. 5, the paragraph after Alg. 2).
 
 Every floating-point quantity is FP64. Readings of passages where the paper is silent
 or differs from this tensor-product, second-order setting are listed in the module

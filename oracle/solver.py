@@ -100,16 +100,27 @@ class SEM:
     def dt_cfl(self, cfl: float = 0.3) -> float:
         return cfl_dt(self.vxy, self.quads, self.c2, self.p, cfl)
 
-    def lambda_max(self, iters: int = 200, seed: int = 11) -> float:
+    def lambda_max(self, iters: int | None = None, seed: int = 11, tol: float = 1e-14,
+                   max_iters: int = 100000) -> float:
         """Largest eigenvalue of M^-1 K by power iteration (M^-1 K is similar to the
-        symmetric M^-1/2 K M^-1/2, so its spectrum is real and non-negative)."""
+        symmetric M^-1/2 K M^-1/2, so its spectrum is real and non-negative).
+
+        With ``iters`` the iteration runs that many times. Otherwise it runs until the
+        estimate has changed by at most ``tol`` (relative) for 20 iterations in a row:
+        the error falls like (lambda_2 / lambda_1)^k, and that ratio is close to 1 on
+        graded meshes."""
         rng = np.random.default_rng(seed)
         x = rng.standard_normal(self.n_nodes)
         lam = 0.0
-        for _ in range(iters):
+        calm = 0
+        for k in range(iters if iters is not None else max_iters):
             y = self.minv * (self.K @ x)
-            lam = float(np.linalg.norm(y) / np.linalg.norm(x))
+            new = float(np.linalg.norm(y) / np.linalg.norm(x))
+            calm = calm + 1 if abs(new - lam) <= tol * new else 0
+            lam = new
             x = y / np.linalg.norm(y)
+            if iters is None and calm >= 20:
+                break
         return lam
 
     def energy(self, u_next, u, v_half):
