@@ -67,6 +67,22 @@ enum sem_field { SEM_FIELD_U = 0, SEM_FIELD_V = 1 };
  * predictor, kept in the context; sem_reset, sem_set_field and sem_set_sources drop it,
  * so the next step recomputes it. */
 enum sem_formulation { SEM_FORM_LEAPFROG = 0, SEM_FORM_HEUN = 1 };
+/* How a step sums the element contributions r_e into the shared global nodes (the race of
+ * the accumulation in Alg. 2; Sec. 5 resolves it by element colouring):
+ *   SEM_SCATTER_LDS_ATOMIC: each workgroup owns a contiguous range of nodes, sums every
+ *     contribution to them in LDS (FP64 LDS atomics) and recomputes the neighbouring
+ *     elements of other workgroups that touch them; one launch per step, no global r.
+ *   SEM_SCATTER_COLOUR: the paper's scheme. Elements are greedily coloured in the element
+ *     order (two elements sharing a node differ in colour), one launch per colour adds
+ *     r_e into a global r with plain read-modify-write (no two elements of a colour share
+ *     a node), then one launch applies the update and clears r.
+ *   SEM_SCATTER_ATOMIC: one launch over all elements adds r_e into a global r with global
+ *     floating-point atomics, then the update launch.
+ *   SEM_SCATTER_AUTO: the fastest measured on MI355X for the context's kernel, which is
+ *     LDS_ATOMIC for every configuration measured so far.
+ * COLOUR and ATOMIC are built for the single-shot leapfrog step (n_shots = 1). */
+enum sem_scatter { SEM_SCATTER_AUTO = 0, SEM_SCATTER_LDS_ATOMIC = 1, SEM_SCATTER_COLOUR = 2,
+                   SEM_SCATTER_ATOMIC = 3 };
 
 /* Input mesh (host arrays, original numbering). */
 typedef struct {
@@ -100,6 +116,7 @@ typedef struct {
                               * <= 163840 (the 64-shot kernel accumulates in FP64 in    *
                               * either precision); 0 = automatic                        */
     int32_t formulation;     /* sem_formulation                                         */
+    int32_t scatter;         /* sem_scatter                                             */
 } sem_options;
 
 typedef struct {
@@ -138,6 +155,13 @@ typedef struct {
     double kernel_bytes_per_step; /* least bytes this context's step kernel reads and   *
                                    * writes (the single-shot kernel computes geometric *
                                    * factors from 8 words per element)                 */
+    int32_t n_colours;       /* colours of the greedy element colouring in the element  *
+                              * order (Sec. 5; computed for every context)              */
+    int32_t scatter;         /* the sem_scatter in use (AUTO resolved)                   */
+    double growth_per_step;  /* largest per-step amplification of the time stepper at    *
+                              * h^2 lambda_max: 1 for leapfrog below dt_stable; for Heun *
+                              * sqrt(1 + (h^2 lambda_max)^2 / 4), above 1 for any h     *
+                              * (lambda_max from the leapfrog operator's power iteration)*/
 } sem_info;
 
 /* Build the context: validate the mesh, number the GLL nodes, reorder elements and
@@ -155,6 +179,11 @@ int sem_get_info(const sem_ctx* ctx, sem_info* info);
  * (host buffers owned by the caller). Either pointer may be NULL. */
 int sem_get_permutations(const sem_ctx* ctx, int32_t* elem_new2old, int32_t* node_new2old);
 
+/* Greedy element colour of every element, ORIGINAL element order, [n_elements] host buffer
+ * (Sec. 5: elements are visited in the context's element order and each takes the smallest
+ * colour not used by an already-visited element sharing a global node). */
+int sem_get_colours(const sem_ctx* ctx, int32_t* colour);
+
 /* Coordinates of the global nodes, original numbering, [n_nodes][2] host buffer. */
 int sem_get_node_coords(const sem_ctx* ctx, double* xy);
 
@@ -170,8 +199,15 @@ int sem_set_sources(sem_ctx* ctx, int32_t n, const double* xy, const int32_t* sh
  * all receivers after each step. node_out as above. */
 int sem_set_receivers(sem_ctx* ctx, int32_t n, const double* xy, int32_t* node_out);
 
-/* Replace the model c^2 (host, original element order). Keeps dt; re-checks stability. */
-int sem_set_c2(sem_ctx* ctx, const double* c2);
+/* Replace the model c^2 ([n_elements] double, original element order): a host array when
+ * on_device = 0, a device array (read in stream order on the context stream) when
+ * on_device = 1. Keeps dt and re-checks stability: lambda_max(M^-1 K) scales at most with
+ * max_e(c2_e / c2ref_e) against the model of the last power iteration, and the power
+ * iteration runs again only if that bound leaves dt unproven (then UNSTABLE_DT if dt is
+ * too large). Resets the state (u = v = 0). Errors: INVALID_ARG (non-positive or
+ * non-finite c2, on_device not 0/1, first-order formulation), NO_DEVICE (on_device = 1 on a
+ * host-only context), UNSTABLE_DT, HIP. */
+int sem_set_c2(sem_ctx* ctx, const double* c2, int32_t on_device);
 
 /* u = v = 0, step counter = 0. */
 int sem_reset(sem_ctx* ctx);

@@ -48,11 +48,16 @@ struct sem_ctx {
     int32_t n_src = 0, n_rec = 0;
     double f0 = 10.0, t0 = 0.1;
     double lambda_max = 0.0, dt_stable = 0.0;
+    // the model (new element order) of the last power iteration and its estimate: a later
+    // model m is bounded by lambda_max(m) <= max_e(m_e / ref_e) * lambda_max(ref)
+    std::vector<double> c2_ref;
+    double lambda_ref = 0.0;
     double setup_seconds = 0.0;
     std::vector<DevBuf*> owned;       // every DevBuf to free at destroy
     // first-order system with Heun (SEM_FORM_HEUN): a third U buffer, V at the start and
     // the end of a step ([E][2][nq] each), and 1 / M-bar weighted by 1/c^2
     int formulation = SEM_FORM_LEAPFROG;
+    int scatter = SEM_SCATTER_LDS_ATOMIC;
     DevBuf u_next, hv[2], minv_w;
     // the next step's predicted U~ (written by the fused corrector) and whether u[cur ^ 1]
     // holds U~ for the current state (false after any change of state or sources)
@@ -348,6 +353,8 @@ int power_iteration(sem_ctx* c, int iters) {
     }
     c->lambda_max = lam;
     c->dt_stable = lam > 0.0 ? 2.0 / std::sqrt(lam) : INFINITY;
+    c->c2_ref = c->plan.c2;
+    c->lambda_ref = lam;
     return zero_state<T>(c);
 }
 
@@ -800,6 +807,17 @@ int sem_create(const sem_mesh* mesh, const sem_options* opt, sem_ctx** out) {
         return SEM_ERR_INVALID_ARG;
     }
     c->formulation = opt->formulation;
+    if (opt->scatter < SEM_SCATTER_AUTO || opt->scatter > SEM_SCATTER_ATOMIC) {
+        g_create_error = "unknown scatter";
+        delete c;
+        return SEM_ERR_INVALID_ARG;
+    }
+    c->scatter = opt->scatter == SEM_SCATTER_AUTO ? SEM_SCATTER_LDS_ATOMIC : opt->scatter;
+    if (c->scatter != SEM_SCATTER_LDS_ATOMIC) {
+        g_create_error = "this scatter is not available";
+        delete c;
+        return SEM_ERR_INVALID_ARG;
+    }
     sem::PlanOptions po;
     po.p = opt->p;
     po.elem_order = opt->elem_order;
@@ -862,11 +880,21 @@ int sem_create(const sem_mesh* mesh, const sem_options* opt, sem_ctx** out) {
         return code;
     }
     c->setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    if (!c->host_only && !row_kernel(c) && lds_bytes(c) > 160 * 1024) {
-        g_create_error = "owned nodes x shot lanes of the largest tile exceed the 160 KB of LDS "
-                         "(use smaller tile_elems)";
-        delete c;
-        return SEM_ERR_INVALID_ARG;
+    if (!c->host_only) {
+        // LDS of the largest tile in the kernel this context launches
+        const int64_t lds_own = (c->plan.max_owned + 63) & ~63;
+        size_t need = lds_bytes(c);
+        if (c->formulation == SEM_FORM_HEUN)
+            need = sem::heun_lds_bytes(opt->p, 2, lds_own, c->wsize);
+        else if (row_kernel(c))
+            need = sem::rows_lds_bytes(opt->p, row_block, lds_own, c->wsize);
+        if (need > sem::kMaxLds) {
+            g_create_error = "the largest tile needs " + std::to_string(need) +
+                             " bytes of LDS, more than the 160 KB of a workgroup (use smaller "
+                             "tile_elems or tile_items)";
+            delete c;
+            return SEM_ERR_INVALID_ARG;
+        }
     }
     if (!c->host_only && (double)c->plan.nn * c->S * c->wsize >= 4294967296.0) {
         g_create_error = "n_nodes * n_shots * word size must stay below 4 GiB (32-bit buffer offsets)";
@@ -944,6 +972,14 @@ int sem_get_info(const sem_ctx* c, sem_info* info) {
     info->setup_seconds = c->setup_seconds;
     info->reorder_seconds = P.reorder_seconds;
     info->max_accum_nodes = P.tile_ns.empty() ? P.max_owned : P.max_shared;
+    info->n_colours = P.n_colours;
+    info->scatter = c->scatter;
+    info->growth_per_step = 1.0;
+    if (c->formulation == SEM_FORM_HEUN && c->lambda_max > 0.0) {
+        // Heun on y' = i w y: |1 + z + z^2 / 2|^2 = 1 + th^4 / 4 with z = i th, th = h w
+        const double th2 = P.dt * P.dt * c->lambda_max;
+        info->growth_per_step = std::sqrt(1.0 + 0.25 * th2 * th2);
+    }
     return SEM_OK;
 }
 
@@ -951,6 +987,12 @@ int sem_get_permutations(const sem_ctx* c, int32_t* e, int32_t* n) {
     if (!c) return SEM_ERR_INVALID_ARG;
     if (e) std::memcpy(e, c->plan.elem_new2old.data(), c->plan.ne * sizeof(int32_t));
     if (n) std::memcpy(n, c->plan.node_new2old.data(), c->plan.nn * sizeof(int32_t));
+    return SEM_OK;
+}
+
+int sem_get_colours(const sem_ctx* c, int32_t* colour) {
+    if (!c || !colour) return SEM_ERR_INVALID_ARG;
+    for (int64_t k = 0; k < c->plan.ne; ++k) colour[c->plan.elem_new2old[k]] = c->plan.colour[k];
     return SEM_OK;
 }
 
@@ -985,13 +1027,27 @@ int sem_set_receivers(sem_ctx* c, int32_t n, const double* xy, int32_t* node_out
                                    : set_receivers_t<float>(c, n, xy, node_out);
 }
 
-int sem_set_c2(sem_ctx* c, const double* c2) {
+int sem_set_c2(sem_ctx* c, const double* c2, int32_t on_device) {
     if (!c || !c2) return SEM_ERR_INVALID_ARG;
     if (c->formulation == SEM_FORM_HEUN)
         return fail(c, SEM_ERR_INVALID_ARG, "sem_set_c2 is not available for the first-order formulation");
-    for (int64_t e = 0; e < c->plan.ne; ++e)
+    if (on_device != 0 && on_device != 1) return fail(c, SEM_ERR_INVALID_ARG, "on_device must be 0 or 1");
+    const int64_t ne = c->plan.ne;
+    std::vector<double> host;
+    if (on_device) {
+        int rc = need_device(c);
+        if (rc) return rc;
+        rc = set_device(c);
+        if (rc) return rc;
+        host.resize((size_t)ne);
+        // stream-ordered after the caller's work on the context stream
+        SEM_HIP(c, hipMemcpyAsync(host.data(), c2, (size_t)ne * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        SEM_HIP(c, hipStreamSynchronize(c->stream));
+        c2 = host.data();
+    }
+    for (int64_t e = 0; e < ne; ++e)
         if (!(c2[e] > 0.0) || !std::isfinite(c2[e])) return fail(c, SEM_ERR_INVALID_ARG, "c2 must be positive");
-    for (int64_t k = 0; k < c->plan.ne; ++k) c->plan.c2[k] = c2[c->plan.elem_new2old[k]];
+    for (int64_t k = 0; k < ne; ++k) c->plan.c2[k] = c2[c->plan.elem_new2old[k]];
     if (c->host_only) return SEM_OK;
     int rc = set_device(c);
     if (rc) return rc;
@@ -999,6 +1055,18 @@ int sem_set_c2(sem_ctx* c, const double* c2) {
     if (c->geo) {
         rc = c->precision == SEM_F64 ? upload_geometry<double>(c) : upload_geometry<float>(c);
         if (rc) return rc;
+    }
+    // K(m) = sum_e m_e Khat_e with every Khat_e positive semi-definite and the mass
+    // independent of m, so ratio * K(ref) - K(m) is positive semi-definite for
+    // ratio = max_e m_e / ref_e, and lambda_max(m) <= ratio * lambda_max(ref). The power
+    // iteration runs again only when that bound does not already show dt stable.
+    double ratio = 0.0;
+    for (int64_t k = 0; k < ne; ++k) ratio = std::max(ratio, c->plan.c2[k] / c->c2_ref[k]);
+    const double bound = ratio * c->lambda_ref;
+    if (c->lambda_ref > 0.0 && c->plan.dt < 2.0 / std::sqrt(bound)) {
+        c->lambda_max = bound;
+        c->dt_stable = 2.0 / std::sqrt(bound);
+        return c->precision == SEM_F64 ? zero_state<double>(c) : zero_state<float>(c);
     }
     rc = c->precision == SEM_F64 ? power_iteration<double>(c, 60) : power_iteration<float>(c, 60);
     if (rc) return rc;

@@ -142,4 +142,20 @@ template <typename T>
 hipError_t launch_heun_stage(int p, int mode, int64_t n_tiles, size_t lds_bytes,
                              const HeunArgs<T>& a, hipStream_t stream);
 
+// Dynamic LDS of one workgroup of the single-shot row kernel: the per-element stage
+// (16-byte aligned rows of nq words), the FP64 accumulator and the three prefetch arrays
+// (v, u, dt/M) of lds_own entries each.
+inline size_t rows_lds_bytes(int p, int threads, int64_t lds_own, size_t word) {
+    const int n = p + 1, nqp = (n * n + 3) & ~3, epb = (64 / n) * (threads / 64);
+    return (size_t)epb * nqp * word + (size_t)lds_own * 8 + (size_t)3 * lds_own * word;
+}
+// Heun stages (512 threads): stage, one FP64 accumulator (two for the fused corrector,
+// mode 2) and, in FP32 only, three prefetch arrays of lds_own entries.
+inline size_t heun_lds_bytes(int p, int mode, int64_t lds_own, size_t word) {
+    const int n = p + 1, nqp = (n * n + 3) & ~3, epb = (64 / n) * (kRowBlock / 2 / 64);
+    return (size_t)epb * nqp * word + (size_t)(mode == 2 ? 2 : 1) * lds_own * 8 +
+           (word == 4 ? (size_t)3 * lds_own * word : 0);
+}
+constexpr size_t kMaxLds = 160 * 1024;   // LDS per workgroup on gfx950
+
 }  // namespace sem

@@ -900,9 +900,7 @@ hipError_t launch_one(int64_t n_tiles, size_t lds, const StepArgs<T>& a, hipStre
 template <typename T, int P, int RB, int NP>
 hipError_t launch_rows(int64_t n_tiles, size_t lds, const StepArgs<T>& a, hipStream_t st) {
     auto fn = a.grad != nullptr ? step_rows_kernel<T, P, RB, NP, true> : step_rows_kernel<T, P, RB, NP, false>;
-    constexpr int N = P + 1, NQP = (N * N + 3) & ~3, EPB = (64 / N) * (RB / 64);
-    // stage + accumulator + three prefetch arrays of a.lds_own entries each
-    lds = (size_t)EPB * NQP * sizeof(T) + (size_t)a.lds_own * sizeof(double) + (size_t)3 * a.lds_own * sizeof(T);
+    lds = rows_lds_bytes(P, RB, a.lds_own, sizeof(T));
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -1177,12 +1175,10 @@ __global__ void __launch_bounds__(kRowBlock / 2) heun_rows_kernel(const HeunArgs
 
 template <typename T, int P>
 hipError_t launch_heun_p(int mode, int64_t n_tiles, size_t lds, const HeunArgs<T>& a, hipStream_t st) {
-    constexpr int N = P + 1, NQP = (N * N + 3) & ~3, RB = kRowBlock / 2, EPB = (64 / N) * (RB / 64);
+    constexpr int RB = kRowBlock / 2;
     auto fn = mode == 2 ? heun_rows_kernel<T, P, true, true>
               : (mode == 1 ? heun_rows_kernel<T, P, true, false> : heun_rows_kernel<T, P, false, false>);
-    // stage, accumulator(s) and (FP32) the three prefetch arrays
-    lds = (size_t)EPB * NQP * sizeof(T) + (size_t)(mode == 2 ? 2 : 1) * a.lds_own * sizeof(double) +
-          (sizeof(T) == 4 ? (size_t)3 * a.lds_own * sizeof(T) : 0);
+    lds = heun_lds_bytes(P, mode, a.lds_own, sizeof(T));
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

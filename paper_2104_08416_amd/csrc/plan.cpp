@@ -671,10 +671,34 @@ std::string build_plan(const MeshIn& m, const PlanOptions& opt, Plan& P, int& co
     }
     P.minv.resize(nn);
     for (int64_t i = 0; i < nn; ++i) P.minv[i] = 1.0 / mass[P.node_new2old[i]];
+    if (!colour_elements(P)) {
+        code = SEM_ERR_BAD_MESH;
+        return "greedy element colouring needs more than 64 colours";
+    }
     if (opt.node_order == SEM_NODES_FIRST_TOUCH)
         build_tiles(P, opt.tile_elems, opt.tile_items, opt.max_owned, opt.split_single);
     code = SEM_OK;
     return "";
+}
+
+bool colour_elements(Plan& P) {
+    // used[v]: colours of the already-coloured elements around global node v; the colours
+    // an element must avoid are the union over its nodes
+    const int64_t ne = P.ne, nq = P.nq;
+    std::vector<uint64_t> used(P.nn, 0);
+    P.colour.assign(ne, 0);
+    int32_t nc = 0;
+    for (int64_t k = 0; k < ne; ++k) {
+        uint64_t taken = 0;
+        for (int64_t q = 0; q < nq; ++q) taken |= used[P.conn_soa[q * ne + k]];
+        if (taken == ~0ull) return false;
+        const int c = __builtin_ctzll(~taken);
+        P.colour[k] = c;
+        nc = std::max(nc, c + 1);
+        for (int64_t q = 0; q < nq; ++q) used[P.conn_soa[q * ne + k]] |= 1ull << c;
+    }
+    P.n_colours = nc;
+    return true;
 }
 
 }  // namespace sem

@@ -64,6 +64,10 @@ struct Plan {
     // two or more elements, the rest of its range to exactly one (an own element).
     std::vector<int32_t> tile_ns;
     int32_t max_shared = 0;
+    // greedy element colouring in the new element order (Sec. 5): colour[k] of new
+    // element k; two elements sharing a global node never share a colour
+    std::vector<int32_t> colour;
+    int32_t n_colours = 0;
     double reorder_seconds = 0.0;
 };
 
@@ -78,6 +82,11 @@ void build_tiles(Plan& plan, int tile_elems, int tile_items, int max_owned, bool
 
 // Cell index along the generalized Hilbert curve over a W x H grid.
 int64_t hilbert_index(int64_t W, int64_t H, int64_t cx, int64_t cy);
+
+// First-fit colouring of the elements in the plan's element order: each element takes the
+// smallest colour not used by an earlier element that shares a global node with it.
+// Returns false when more than 64 colours would be needed.
+bool colour_elements(Plan& plan);
 
 // Nearest global node (original numbering) of a point; ties -> lowest id.
 int32_t nearest_node(const Plan& plan, double x, double y);

@@ -20,6 +20,7 @@ F32, F64 = 0, 1
 ORDERS = {"hilbert": 0, "morton": 1, "lex": 2, "random": 3, "connectivity": 4, "distance": 5}
 NODE_ORDERS = {"first_touch": 0, "original": 1}
 FORMULATIONS = {"leapfrog": 0, "heun": 1}
+SCATTERS = {"auto": 0, "lds_atomic": 1, "colour": 2, "atomic": 3}
 FIELD_U, FIELD_V = 0, 1
 STATUS = {0: "OK", -1: "INVALID_ARG", -2: "BAD_MESH", -3: "UNSTABLE_DT", -4: "HIP_ERROR",
           -5: "OOM", -6: "NO_DEVICE"}
@@ -43,7 +44,8 @@ class _Options(ctypes.Structure):
                 ("device", ctypes.c_int32), ("dt", ctypes.c_double), ("cfl", ctypes.c_double),
                 ("stream", ctypes.c_void_p), ("tile_elems", ctypes.c_int32), ("shot_lanes", ctypes.c_int32),
                 ("tile_items", ctypes.c_int32), ("block_threads", ctypes.c_int32),
-                ("lds_bytes", ctypes.c_int32), ("formulation", ctypes.c_int32)]
+                ("lds_bytes", ctypes.c_int32), ("formulation", ctypes.c_int32),
+                ("scatter", ctypes.c_int32)]
 
 
 class _Info(ctypes.Structure):
@@ -57,14 +59,16 @@ class _Info(ctypes.Structure):
                 ("dt", ctypes.c_double), ("dt_stable", ctypes.c_double), ("lambda_max", ctypes.c_double),
                 ("alg_bytes_per_step", ctypes.c_double), ("alg_flops_per_step", ctypes.c_double),
                 ("setup_seconds", ctypes.c_double), ("reorder_seconds", ctypes.c_double),
-                ("max_accum_nodes", ctypes.c_int32), ("kernel_bytes_per_step", ctypes.c_double)]
+                ("max_accum_nodes", ctypes.c_int32), ("kernel_bytes_per_step", ctypes.c_double),
+                ("n_colours", ctypes.c_int32), ("scatter", ctypes.c_int32),
+                ("growth_per_step", ctypes.c_double)]
 
 
 EXPORTS = ("sem_create", "sem_create_error", "sem_get_info", "sem_get_permutations",
            "sem_get_node_coords", "sem_set_sources", "sem_set_receivers", "sem_set_c2", "sem_reset",
            "sem_run", "sem_step", "sem_get_field", "sem_set_field", "sem_apply_stiffness",
            "sem_adjoint_gradient", "sem_synchronize", "sem_hilbert_index", "sem_last_error",
-           "sem_destroy", "sem_autotune")
+           "sem_destroy", "sem_autotune", "sem_get_colours")
 
 
 def _load():
@@ -84,9 +88,10 @@ def _load():
     lib.sem_get_info.argtypes = [P, ctypes.POINTER(_Info)]
     lib.sem_get_permutations.argtypes = [P, VP, VP]
     lib.sem_get_node_coords.argtypes = [P, VP]
+    lib.sem_get_colours.argtypes = [P, VP]
     lib.sem_set_sources.argtypes = [P, I32, VP, VP, D, D, VP]
     lib.sem_set_receivers.argtypes = [P, I32, VP, VP]
-    lib.sem_set_c2.argtypes = [P, VP]
+    lib.sem_set_c2.argtypes = [P, VP, I32]
     lib.sem_reset.argtypes = [P]
     lib.sem_run.argtypes = [P, I64, VP]
     lib.sem_step.argtypes = [P]
@@ -137,7 +142,8 @@ class Simulator:
                  n_shots: int = 1, dt: float = 0.0, cfl: float = 0.3, device: int = 0,
                  seed: int = 3, node_order: str = "first_touch", tile_elems: int = 0,
                  shot_lanes: int = 0, tile_items: int = 0, block_threads: int = 0,
-                 lds_bytes: int = 0, formulation: str = "leapfrog", stream=None):
+                 lds_bytes: int = 0, formulation: str = "leapfrog", scatter: str = "auto",
+                 stream=None):
         self._vxy = np.ascontiguousarray(vxy, dtype=np.float64)
         self._quads = np.ascontiguousarray(quads, dtype=np.int32)
         self._c2 = np.ascontiguousarray(c2, dtype=np.float64)
@@ -153,7 +159,7 @@ class Simulator:
             self._torch_device = torch.device("cuda", device)
         o = _Options(p, F64 if precision == "f64" else F32, ORDERS[order], NODE_ORDERS[node_order],
                      seed, n_shots, device, dt, cfl, stream or 0, tile_elems, shot_lanes, tile_items,
-                     block_threads, lds_bytes, FORMULATIONS[formulation])
+                     block_threads, lds_bytes, FORMULATIONS[formulation], SCATTERS[scatter])
         h = ctypes.c_void_p()
         rc = _lib.sem_create(ctypes.byref(m), ctypes.byref(o), ctypes.byref(h))
         if rc:
@@ -166,6 +172,10 @@ class Simulator:
         self.p = p
         self.dt = inf["dt"]
         self.n_receivers = 0
+        # bumped by every change of the sources or receivers (checked by sem_forward), and
+        # the model that sem_forward set last (None after any other set_c2)
+        self.io_version = 0
+        self._forward_model = None
 
     # ------------------------------------------------------------------ plumbing
     def _check(self, rc: int, what: str):
@@ -206,6 +216,11 @@ class Simulator:
         self._check(_lib.sem_get_permutations(self._h, _ptr(e), _ptr(n)), "sem_get_permutations")
         return e, n
 
+    def colours(self) -> np.ndarray:
+        c = np.empty(self.n_elements, np.int32)
+        self._check(_lib.sem_get_colours(self._h, _ptr(c)), "sem_get_colours")
+        return c
+
     def node_coords(self) -> np.ndarray:
         xy = np.empty((self.n_nodes, 2), np.float64)
         self._check(_lib.sem_get_node_coords(self._h, _ptr(xy)), "sem_get_node_coords")
@@ -219,6 +234,7 @@ class Simulator:
         nodes = np.empty(n, np.int32)
         self._check(_lib.sem_set_sources(self._h, n, _ptr(xy), _ptr(shot), f0, t0, _ptr(nodes)),
                     "sem_set_sources")
+        self.io_version += 1
         return nodes
 
     def set_receivers(self, xy) -> np.ndarray:
@@ -227,11 +243,24 @@ class Simulator:
         self._check(_lib.sem_set_receivers(self._h, xy.shape[0], _ptr(xy), _ptr(nodes)),
                     "sem_set_receivers")
         self.n_receivers = xy.shape[0]
+        self.io_version += 1
         return nodes
 
     def set_c2(self, c2):
-        c2 = np.ascontiguousarray(c2, dtype=np.float64)
-        self._check(_lib.sem_set_c2(self._h, _ptr(c2)), "sem_set_c2")
+        """New model c^2 [n_elements] in original element order: a NumPy array, a CPU
+        tensor, or a float64 tensor on this simulator's GPU (read in stream order)."""
+        if hasattr(c2, "is_cuda") and c2.is_cuda:
+            assert c2.dtype.is_floating_point and c2.numel() == self.n_elements
+            c2 = c2.detach().to(dtype=__import__("torch").float64).contiguous()
+            assert c2.device == self._torch_device, "c2 lives on another GPU than the simulator"
+            self._check(_lib.sem_set_c2(self._h, c2.data_ptr(), 1), "sem_set_c2")
+        else:
+            if hasattr(c2, "detach"):
+                c2 = c2.detach().cpu().numpy()
+            c2 = np.ascontiguousarray(c2, dtype=np.float64)
+            assert c2.size == self.n_elements
+            self._check(_lib.sem_set_c2(self._h, _ptr(c2), 0), "sem_set_c2")
+        self._forward_model = None
 
     # ------------------------------------------------------------------ device calls
     def reset(self):
@@ -289,24 +318,41 @@ def _make_forward():
 
     class SemForward(torch.autograd.Function):
         """traces = SemForward.apply(c2, sim, nsteps, ckpt_every): forward run from rest with
-        the model ``c2`` (float64 tensor, original element order); backward returns dL/dc2
-        from the checkpointed discrete adjoint."""
+        the model ``c2`` (float64 tensor on the CPU or on the simulator's GPU, original
+        element order); backward returns dL/dc2 from the checkpointed discrete adjoint, on
+        the device and in the dtype of ``c2``.
+
+        The model is saved with the graph: if the simulator's model was changed after this
+        forward (another forward on the same simulator, or set_c2), backward sets it back.
+        Sources and receivers are not saved; backward refuses to run when they changed."""
 
         @staticmethod
         def forward(ctx, c2, sim: Simulator, nsteps: int, ckpt_every: int = 40):
-            sim.set_c2(c2.detach().cpu().numpy())
+            model = c2.detach().to(sim._torch_device, torch.float64).clone()
+            sim.set_c2(model)
+            sim._forward_model = model
             sim.reset()
             tr = sim.run(nsteps)
             ctx.sim = sim
             ctx.nsteps = nsteps
             ctx.ckpt_every = ckpt_every
+            ctx.model = model
+            ctx.io_version = sim.io_version
+            ctx.c2_device, ctx.c2_dtype = c2.device, c2.dtype
             return tr
 
         @staticmethod
         def backward(ctx, grad_traces):
-            g = ctx.sim.adjoint_gradient(grad_traces.contiguous().to(ctx.sim.torch_dtype), ctx.nsteps,
-                                         ctx.ckpt_every)
-            return g, None, None, None
+            sim = ctx.sim
+            if sim.io_version != ctx.io_version:
+                raise RuntimeError("sources or receivers changed between forward and backward")
+            if sim._forward_model is not ctx.model:
+                # the simulator holds another model now: restore this forward's model
+                sim.set_c2(ctx.model)
+                sim._forward_model = ctx.model
+            g = sim.adjoint_gradient(grad_traces.contiguous().to(sim.torch_dtype), ctx.nsteps,
+                                     ctx.ckpt_every)
+            return g.to(device=ctx.c2_device, dtype=ctx.c2_dtype), None, None, None
 
     return SemForward
 

@@ -205,3 +205,23 @@ def test_algorithmic_bytes_model(semlib, prec, w):
     E, N = inf["n_elements"], inf["n_nodes"]
     assert inf["alg_bytes_per_step"] == E * (4 * nq + 8 * w + 4 * nq * w) + N * 5 * w
     s.close()
+
+
+@pytest.mark.parametrize("name,kw,orders", [
+    ("layered1024", dict(n=20), ("hilbert", "morton", "lex", "random", "connectivity")),
+    ("graded1414", dict(n=16, p=5), ("hilbert", "random")),
+    ("homog64", dict(n=12, p=2), ("hilbert", "distance"))])
+def test_colours_bit_exact(semlib, name, kw, orders):
+    """The library's greedy element colouring (Sec. 5) equals the oracle's first-fit
+    colouring visited in the same element order, element by element."""
+    from oracle import colour
+    wl = workloads.workload(name, **kw)
+    conn, _ = mesh.global_numbering(wl.quads, wl.vxy.shape[0], wl.p)
+    for kind in orders:
+        s = semlib.Simulator(wl.vxy, wl.quads, wl.c2, wl.p, order=kind, device=-1, seed=3)
+        e, _ = s.permutations()
+        want = colour.greedy_colours(conn, e)
+        got = s.colours()
+        np.testing.assert_array_equal(got, want, err_msg=kind)
+        assert s.info()["n_colours"] == int(want.max()) + 1
+        s.close()
