@@ -41,7 +41,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
-ALL_LEGS = ("main", "fp64", "heun", "batch", "adjoint", "orders", "graded", "cpu")
+ALL_LEGS = ("main", "fp64", "scatter", "heun", "batch", "adjoint", "orders", "graded", "cpu")
+CHUNKS = 5                     # the timed steps are event-timed in this many chunks (median)
 KERNEL_SOURCES = ("kernels.hip", "kernels.h", "api.hip", "plan.cpp", "plan.h")
 HEADLINE_PROFILE = os.path.join(ROOT, "profiles", "step_rows_kernel_layered1024_f32_hilbert.md")
 COPY_BYTES = 1 << 30           # the calibration copy reads and writes 1 GiB each
@@ -61,22 +62,32 @@ def make_sim(sem, wl, precision, order="hilbert", n_shots=None, **kw):
 
 
 def time_steps(torch, sim, steps, warmup, record=True):
-    """Average time of one step over ``steps`` launches, HIP events on the sim's stream."""
+    """Time ``steps`` launches after ``warmup`` untimed ones, with HIP events on the sim's
+    stream around the whole run and around each of CHUNKS equal chunks of it. Returns the
+    mean time per step over the whole run, the traces, and the median of the chunk means."""
     sim.reset()
     sim.run(warmup, record=False)
     traces = None
     if record and sim.n_receivers:
         traces = torch.empty((sim.n_shots, sim.n_receivers, steps), dtype=sim.torch_dtype, device="cuda")
+    chunks = max(1, min(CHUNKS, steps))
+    bounds = [steps * k // chunks for k in range(chunks + 1)]
+    # one trace buffer per chunk, allocated before the timed region
+    parts = [torch.empty((sim.n_shots, sim.n_receivers, bounds[k + 1] - bounds[k]), dtype=sim.torch_dtype,
+                         device="cuda") if traces is not None else None for k in range(chunks)]
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    ev0.record(stream)
-    sim.run(steps, traces=traces, record=record)
-    ev1.record(stream)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(chunks + 1)]
+    evs[0].record(stream)
+    for k in range(chunks):
+        sim.run(bounds[k + 1] - bounds[k], traces=parts[k], record=record)
+        evs[k + 1].record(stream)
     torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1)
-    return ms / 1e3 / steps, traces
+    if traces is not None:
+        torch.cat(parts, dim=2, out=traces)
+    total = evs[0].elapsed_time(evs[-1]) / 1e3 / steps
+    per = sorted(evs[k].elapsed_time(evs[k + 1]) / 1e3 / (bounds[k + 1] - bounds[k]) for k in range(chunks))
+    return total, traces, per[len(per) // 2]
 
 
 def leg_summary(sim, sec_per_step, label):
@@ -209,8 +220,7 @@ def profile_summary(d, kernel, steps, counter_steps):
     return "\n".join(out)
 
 
-def cpu_baseline(n=256, steps=1000):
-    """FP64 CPU oracle on an n x n-element section of the layered jittered p=4 workload."""
+def _oracle_section(n):
     import workloads
     from oracle import solver
     wl = workloads.workload("layered1024", n=n)
@@ -220,19 +230,58 @@ def cpu_baseline(n=256, steps=1000):
     dt = o.dt_cfl()
     src = solver.snap_to_nodes(wl.src_xy, o.node_xy)
     rec = solver.snap_to_nodes(wl.rec_xy, o.node_xy)
+    return wl, o, dt, src, rec, t_setup
+
+
+def _oracle_worker(args):
+    """One process of the all-core oracle run: its own copy of the section, timed steps."""
+    n, steps = args
+    wl, o, dt, src, rec, _ = _oracle_section(n)
+    o.run(2, dt, src, [0], wl.f0, rec_nodes=rec)
+    t0 = time.perf_counter()
+    o.run(steps, dt, src, [0], wl.f0, rec_nodes=rec)
+    return o.n_nodes, steps, time.perf_counter() - t0
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(n=256, steps=1000, all_core_steps=200):
+    """FP64 CPU oracle on an n x n-element section of the layered jittered p=4 workload: one
+    process on one core, then one process per core (up to 16, the host share of one GPU)
+    each stepping its own copy of the section (the oracle itself is single-threaded)."""
+    import multiprocessing as mp
+    wl, o, dt, src, rec, t_setup = _oracle_section(n)
     o.run(2, dt, src, [0], wl.f0, rec_nodes=rec)
     t0 = time.perf_counter()
     o.run(steps, dt, src, [0], wl.f0, rec_nodes=rec)
     t = time.perf_counter() - t0
+    nodes = o.n_nodes
+    del o
+    cores = max(1, min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()))
+    with mp.get_context("fork").Pool(cores) as pool:
+        res = pool.map(_oracle_worker, [(n, all_core_steps)] * cores)
+    all_rate = sum(nn * st / sec for nn, st, sec in res) / 1e9
     return {
-        "value": o.n_nodes * steps / t / 1e9,
+        "value": nodes * steps / t / 1e9,
         "unit": "GDOF*steps/s",
         "cores": 1,
         "kind": "oracle",
         "sample": (f"FP64 oracle (scipy CSR stiffness, numpy update), {n}x{n}-element section of "
-                   f"the layered jittered p=4 workload ({o.n_nodes} nodes), {steps} steps after "
+                   f"the layered jittered p=4 workload ({nodes} nodes), {steps} steps after "
                    f"2 warm-up steps; operator assembly ({t_setup:.1f} s) excluded"),
         "sec_per_step": t / steps,
+        "cpu_model": cpu_model(),
+        "all_cores": {"value": all_rate, "cores": cores,
+                      "sample": f"{cores} processes, each its own copy of the same section, "
+                                f"{all_core_steps} steps each, aggregate node-steps/s"},
     }
 
 
@@ -252,8 +301,10 @@ def main():
                     help="headline workload (default: the layered 1024^2 p=4 mesh)")
     ap.add_argument("--formulation", default="leapfrog", choices=["leapfrog", "heun"],
                     help="headline formulation: second-order leapfrog or the first-order system with Heun")
+    ap.add_argument("--scatter", default="auto", choices=["auto", "lds_atomic", "colour", "atomic"],
+                    help="headline scatter: owner-tile LDS (auto), colour passes or global atomics")
     ap.add_argument("--copy-calib", action="store_true",
-                    help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
+                    help="run only the 1 GiB device copy with the headline (for the counter runs)")
     ap.add_argument("--profile-summary", default=None, metavar="DIR",
                     help="summarise rocprofv3 CSV output under DIR (no GPU) and exit")
     ap.add_argument("--kernel", default="step_rows_kernel", help="kernel of --profile-summary")
@@ -269,54 +320,81 @@ def main():
         sys.exit(2)
     legs = ("main",) if args.quick else tuple(x for x in args.legs.split(",") if x)
 
+    cpu = None
+    if "cpu" in legs:
+        # first, so that its worker processes fork before this process touches the GPU
+        log("[bench] cpu_baseline leg (oracle, one core then all cores)")
+        cpu = cpu_baseline()
+
     import torch
     import workloads
     from paper_2104_08416_amd import sem
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     out = {}
+    # plain device copy of 2^28 floats (1 GiB read + 1 GiB written per launch): the HBM rate
+    # a streaming kernel reaches on this machine, and the reference of the counter scaling
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    ev1.record()
+    torch.cuda.synchronize()
+    sec = ev0.elapsed_time(ev1) / 1e3 / 5
+    copy_gbs = 2 * 4 * (1 << 28) / sec / 1e9
+    out["copy_calib"] = {"bytes_per_launch": 2 * 4 * (1 << 28), "GBs": copy_gbs}
+    del src, dst
     if args.copy_calib:
-        # plain copy of 2^28 floats (1 GiB read + 1 GiB written per launch), timed
-        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(2):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        ev0.record()
-        for _ in range(5):
-            dst.copy_(src)
-        ev1.record()
-        torch.cuda.synchronize()
-        sec = ev0.elapsed_time(ev1) / 1e3 / 5
-        out["copy_calib"] = {"bytes_per_launch": 2 * 4 * (1 << 28), "GBs": 2 * 4 * (1 << 28) / sec / 1e9}
-        del src, dst
+        legs = ("main",)
     # ---------------------------------------------------------------- headline
     wl = workloads.workload(args.workload, n=args.n)
     label = f"{args.workload} n={wl.nx} p={wl.p} {args.precision} {args.order} S={wl.n_shots}"
     if args.formulation != "leapfrog":
         label += f" {args.formulation}"
+    if args.scatter != "auto":
+        label += f" scatter={args.scatter}"
     log(f"[bench] headline: {label}, setup ...")
-    sim, t_setup = make_sim(sem, wl, args.precision, args.order, formulation=args.formulation)
+    sim, t_setup = make_sim(sem, wl, args.precision, args.order, formulation=args.formulation,
+                            scatter=args.scatter)
     log(f"[bench] setup {t_setup:.1f} s, timing {args.steps} steps")
-    sps, _ = time_steps(torch, sim, args.steps, args.warmup)
+    sps, _, sps_med = time_steps(torch, sim, args.steps, args.warmup)
     main_leg = leg_summary(sim, sps, label)
+    main_leg["median_chunk_us_per_step"] = sps_med * 1e6
     log(f"[bench] headline {main_leg['gdof_steps_per_s']:.1f} GDOF*steps/s, {main_leg['us_per_step']:.1f} us/step")
     sim.close()
 
     if "fp64" in legs:
         log("[bench] fp64 leg")
         s64, _ = make_sim(sem, wl, "f64", "hilbert")
-        sps64, _ = time_steps(torch, s64, min(args.steps, 300), args.warmup)
+        sps64, _, _ = time_steps(torch, s64, min(args.steps, 300), args.warmup)
         out["fp64"] = leg_summary(s64, sps64, "layered1024 p4 f64 hilbert S=1")
         s64.close()
+    if "scatter" in legs:
+        # the paper's colouring (one launch per colour, plain read-modify-write of a global r,
+        # then a node pass) and global atomics, against the owner-tile LDS scatter
+        out["scatter"] = {"lds_atomic": {"us_per_step": main_leg["us_per_step"],
+                                         "gdof_steps_per_s": main_leg["gdof_steps_per_s"]}}
+        for sc in ("colour", "atomic"):
+            log(f"[bench] scatter {sc}")
+            sc_sim, _ = make_sim(sem, wl, "f32", "hilbert", scatter=sc)
+            spc, _, _ = time_steps(torch, sc_sim, min(args.steps, 200), 5)
+            lg = leg_summary(sc_sim, spc, f"scatter {sc}")
+            out["scatter"][sc] = {"us_per_step": lg["us_per_step"], "gdof_steps_per_s": lg["gdof_steps_per_s"],
+                                  "n_colours": sc_sim.info()["n_colours"],
+                                  "time_vs_lds_atomic": lg["us_per_step"] / main_leg["us_per_step"]}
+            sc_sim.close()
     if "orders" in legs:
         out["orders"] = {"hilbert": {k: main_leg[k] for k in ("gdof_steps_per_s", "hbm_frac", "halo_ratio",
                                                               "setup_s", "reorder_s")}}
         for order in ("morton", "lex", "random", "connectivity", "distance"):
             log(f"[bench] order {order}")
             so, _ = make_sim(sem, wl, "f32", order)
-            spo, _ = time_steps(torch, so, min(args.steps, 200), 5)
+            spo, _, _ = time_steps(torch, so, min(args.steps, 200), 5)
             lg = leg_summary(so, spo, order)
             out["orders"][order] = {k: lg[k] for k in ("gdof_steps_per_s", "hbm_frac", "halo_ratio",
                                                        "setup_s", "reorder_s")}
@@ -324,7 +402,7 @@ def main():
     if "heun" in legs:
         log("[bench] heun leg: the first-order u-v system with Heun, layered1024 p=4 FP32")
         sh, _ = make_sim(sem, wl, "f32", "hilbert", formulation="heun")
-        sph, _ = time_steps(torch, sh, min(args.steps, 200), args.warmup)
+        sph, _, _ = time_steps(torch, sh, min(args.steps, 200), args.warmup)
         out["heun"] = leg_summary(sh, sph, "layered1024 p4 f32 hilbert S=1 first-order Heun")
         out["heun"]["time_ratio_vs_leapfrog"] = sph / (main_leg["us_per_step"] / 1e6)
         sh.close()
@@ -334,7 +412,7 @@ def main():
         out["graded"] = {}
         for order in ("hilbert", "morton", "random"):
             sg, _ = make_sim(sem, wg, "f32", order)
-            spg, _ = time_steps(torch, sg, min(args.steps, 100), 5)
+            spg, _, _ = time_steps(torch, sg, min(args.steps, 100), 5)
             lg = leg_summary(sg, spg, f"graded1414 p5 f32 {order}")
             out["graded"][order] = {k: lg[k] for k in ("gdof_steps_per_s", "us_per_step", "hbm_frac",
                                                        "halo_ratio", "setup_s", "reorder_s")}
@@ -343,12 +421,12 @@ def main():
         log("[bench] batch leg: 512^2 p=4, 64 shots FP32 vs single-shot FP64")
         wb = workloads.workload("batch512")
         sb, _ = make_sim(sem, wb, "f32", "hilbert")
-        spb, _ = time_steps(torch, sb, min(args.steps, 200), 10)
+        spb, _, _ = time_steps(torch, sb, min(args.steps, 200), 10)
         out["batch64"] = leg_summary(sb, spb, "batch512 p4 f32 hilbert S=64")
         sb.close()
         w1 = workloads.workload("batch512", n_shots=1)
         s1, _ = make_sim(sem, w1, "f64", "hilbert")
-        sp1, _ = time_steps(torch, s1, min(args.steps, 300), 10)
+        sp1, _, _ = time_steps(torch, s1, min(args.steps, 300), 10)
         out["batch64"]["single_shot_f64"] = leg_summary(s1, sp1, "batch512 p4 f64 hilbert S=1")
         out["batch64"]["speedup_vs_single_shot_f64"] = (
             out["batch64"]["gdof_steps_per_s"] / out["batch64"]["single_shot_f64"]["gdof_steps_per_s"])
@@ -373,11 +451,15 @@ def main():
                           "steps": n, "ckpt_every": wa.ckpt_every, "n_shots": wa.n_shots,
                           "grad_finite": bool(torch.isfinite(g).all().item())}
         sa.close()
-    cpu = None
-    if "cpu" in legs:
-        log("[bench] cpu_baseline leg (oracle)")
-        cpu = cpu_baseline()
-
+    traffic = headline_traffic() if (args.workload, args.precision, args.order, args.n, args.scatter,
+                                      args.formulation) == ("layered1024", "f32", "hilbert", None, "auto",
+                                                            "leapfrog") else None
+    sec = main_leg["us_per_step"] / 1e6
+    # the same step against what it measurably moves and against the box's copy rate
+    main_leg["measured_traffic_GBs"] = traffic / sec / 1e9 if traffic else None
+    main_leg["measured_traffic_frac_of_peak"] = traffic / sec / 1e9 / HBM_PEAK_GBS if traffic else None
+    main_leg["copy_GBs"] = copy_gbs
+    main_leg["achieved_frac_of_copy"] = main_leg["achieved_GBs"] / copy_gbs
     line = {
         "metric": "SEM GDOF*steps/s (FP32 single-shot, Hilbert order); FP64, 64-shot batch, "
                   "adjoint cost and % HBM as extra fields",
@@ -398,9 +480,7 @@ def main():
                    "n_nodes": main_leg["n_nodes"], "n_elements": main_leg["n_elements"],
                    "tile_elems": main_leg["tile_elems"], "parallelism": "1 GPU"},
         "roofline": {"bound": "hbm", "achieved": main_leg["achieved_GBs"], "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": main_leg["hbm_frac"],
-                     "traffic": headline_traffic() if (args.workload, args.precision, args.order, args.n)
-                     == ("layered1024", "f32", "hilbert", None) else None},
+                     "unit": "GB/s", "frac": main_leg["hbm_frac"], "traffic": traffic},
         "cpu_baseline": cpu,
         "main": main_leg,
     }

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <numeric>
 #include <random>
 #include <string>
 #include <vector>
@@ -64,6 +65,12 @@ struct sem_ctx {
     DevBuf u_pred;
     bool heun_pred_valid = false;
     std::vector<DevBuf> extra;        // scratch owned by the adjoint driver
+    // global-accumulator scatter (COLOUR, ATOMIC): r [N] (zero between steps), the point
+    // lists with new node ids, the element array position -> new element index, and the
+    // launch ranges of the element arrays (one per colour; [0, E) for ATOMIC)
+    DevBuf racc, src_node, rec_node;
+    std::vector<int32_t> elem_slot;
+    std::vector<int64_t> ranges;
 };
 
 namespace {
@@ -164,8 +171,41 @@ bool row_kernel(const sem_ctx* c);
 
 // One step-kernel launch over all tiles. The row kernel (one shot lane) keeps the state
 // shot-major [S][N] and is launched once per shot with every per-shot array offset.
+// Global-accumulator step (scatter COLOUR or ATOMIC, one shot): point terms into r, one
+// element launch per range (per colour, or all elements), the node pass, then traces.
+template <typename T>
+int global_launch(sem_ctx* c, const sem::StepArgs<T>& a0) {
+    const sem::Plan& P = c->plan;
+    sem::StepArgs<T> a = a0;
+    a.racc = (T*)c->racc.p;
+    a.shot = 0;
+    if (a.src_b != nullptr && c->n_src > 0) {
+        a.src_node = (const int32_t*)c->src_node.p;
+        a.n_src_pts = c->n_src;
+    } else {
+        a.src_node = nullptr;
+    }
+    if ((a.inj != nullptr || a.trace != nullptr) && c->n_rec > 0) {
+        a.rec_node = (const int32_t*)c->rec_node.p;
+        a.rec_idx = (const int32_t*)c->rec_idx.p;
+        a.n_rec_pts = c->n_rec;
+    }
+    if (a.src_node != nullptr || (a.inj != nullptr && c->n_rec > 0))
+        SEM_HIP(c, sem::launch_global_points<T>(a, 0, c->stream));
+    const int threads = c->geo / 8;
+    for (size_t r = 0; r + 1 < c->ranges.size(); ++r) {
+        a.e_begin = (int32_t)c->ranges[r];
+        a.e_count = (int32_t)(c->ranges[r + 1] - c->ranges[r]);
+        SEM_HIP(c, sem::launch_elems<T>(P.p, threads, c->scatter == SEM_SCATTER_ATOMIC, a, c->stream));
+    }
+    SEM_HIP(c, sem::launch_node_update<T>(a, P.nn, c->stream));
+    if (a.trace != nullptr && c->n_rec > 0) SEM_HIP(c, sem::launch_global_points<T>(a, 1, c->stream));
+    return SEM_OK;
+}
+
 template <typename T>
 int launch(sem_ctx* c, const sem::StepArgs<T>& a) {
+    if (c->scatter != SEM_SCATTER_LDS_ATOMIC) return global_launch<T>(c, a);
     const int64_t nt = (int64_t)c->plan.tile_eb.size() - 1;
     if (!row_kernel(c) || c->S == 1) {
         SEM_HIP(c, sem::launch_step<T>(c->plan.p, c->SL, c->geo, nt, lds_bytes(c), a, c->stream));
@@ -295,6 +335,7 @@ int zero_state(sem_ctx* c) {
     const int64_t n = c->plan.nn * (int64_t)c->S;
     for (int k = 0; k < 2; ++k) SEM_HIP(c, sem::launch_fill<T>((T*)c->u[k].p, T(0), n, c->stream));
     SEM_HIP(c, sem::launch_fill<T>((T*)c->v.p, T(0), n, c->stream));
+    if (c->racc.p) SEM_HIP(c, sem::launch_fill<T>((T*)c->racc.p, T(0), c->plan.nn, c->stream));
     if (c->formulation == SEM_FORM_HEUN && c->u_next.p && c->hv[0].p && c->hv[1].p) {
         const int64_t nvq = 2 * (int64_t)c->plan.nq * c->plan.ne;
         SEM_HIP(c, sem::launch_fill<T>((T*)c->u_next.p, T(0), n, c->stream));
@@ -411,12 +452,15 @@ int upload_geometry(sem_ctx* c) {
         return SEM_OK;
     }
     if (row_kernel(c)) {
+        // position k of the element arrays holds new element elem_slot[k] (the curve order,
+        // or for the COLOUR scatter the colour classes one after another, each in curve order)
         std::vector<int32_t> cb((size_t)ne * nq);
         std::vector<double> gb((size_t)ne * 8, 0.0);
-        for (int64_t e = 0; e < ne; ++e) {
-            for (int64_t q = 0; q < nq; ++q) cb[e * nq + q] = P.conn_soa[q * ne + e];
-            for (int64_t k = 0; k < 6; ++k) gb[e * 8 + k] = P.bilin[k * ne + e];
-            gb[e * 8 + 6] = P.c2[e];
+        for (int64_t k = 0; k < ne; ++k) {
+            const int64_t e = c->elem_slot[k];
+            for (int64_t q = 0; q < nq; ++q) cb[k * nq + q] = P.conn_soa[q * ne + e];
+            for (int64_t j = 0; j < 6; ++j) gb[k * 8 + j] = P.bilin[j * ne + e];
+            gb[k * 8 + 6] = P.c2[e];
         }
         SEM_HIP(c, upload(c, c->conn, cb));
         SEM_HIP(c, upload_real(c, c->G, gb));
@@ -453,10 +497,13 @@ int upload_mesh(sem_ctx* c) {
     if (h.empty()) h.push_back(0);
     SEM_HIP(c, upload(c, c->halo, h));
     SEM_HIP(c, upload(c, c->n2o_node, P.node_new2old));
-    SEM_HIP(c, upload(c, c->n2o_elem, P.elem_new2old));
+    std::vector<int32_t> e2o(P.ne);
+    for (int64_t k = 0; k < P.ne; ++k) e2o[k] = P.elem_new2old[c->elem_slot[k]];
+    SEM_HIP(c, upload(c, c->n2o_elem, e2o));
     const size_t state = (size_t)P.nn * c->S * sizeof(T);
     for (int k = 0; k < 2; ++k) SEM_HIP(c, dev_alloc(c->u[k], state));
     SEM_HIP(c, dev_alloc(c->v, state));
+    if (c->scatter != SEM_SCATTER_LDS_ATOMIC) SEM_HIP(c, dev_alloc(c->racc, (size_t)P.nn * sizeof(T)));
     return zero_state<T>(c);
 }
 
@@ -545,13 +592,14 @@ int set_sources_t(sem_ctx* c, int32_t n, const double* xy, const int32_t* shot, 
         else
             merged.push_back(e);
     }
-    std::vector<int32_t> b(nt + 1, 0), loc, sh;
+    std::vector<int32_t> b(nt + 1, 0), loc, sh, node;
     std::vector<double> w;
     for (const Ent& e : merged) {
         b[e.tile + 1]++;
         loc.push_back(e.loc);
         sh.push_back(e.shot);
         w.push_back(e.w);
+        node.push_back(P.tile_nb[e.tile] + e.loc);
     }
     for (int64_t t = 0; t < nt; ++t) b[t + 1] += b[t];
     c->n_src = (int32_t)merged.size();
@@ -560,6 +608,7 @@ int set_sources_t(sem_ctx* c, int32_t n, const double* xy, const int32_t* shot, 
     SEM_HIP(c, upload(c, c->src_loc, loc));
     SEM_HIP(c, upload(c, c->src_shot, sh));
     SEM_HIP(c, upload_real(c, c->src_w, w));
+    SEM_HIP(c, upload(c, c->src_node, node));
     return SEM_OK;
 }
 
@@ -577,11 +626,12 @@ int set_receivers_t(sem_ctx* c, int32_t n, const double* xy, int32_t* node_out) 
         ents.push_back({t, nw - P.tile_nb[t], i});
     }
     std::stable_sort(ents.begin(), ents.end(), [](const Ent& a, const Ent& b) { return a.tile < b.tile; });
-    std::vector<int32_t> b(nt + 1, 0), loc, idx;
+    std::vector<int32_t> b(nt + 1, 0), loc, idx, node;
     for (const Ent& e : ents) {
         b[e.tile + 1]++;
         loc.push_back(e.loc);
         idx.push_back(e.r);
+        node.push_back(P.tile_nb[e.tile] + e.loc);
     }
     for (int64_t t = 0; t < nt; ++t) b[t + 1] += b[t];
     c->n_rec = n;
@@ -589,6 +639,7 @@ int set_receivers_t(sem_ctx* c, int32_t n, const double* xy, int32_t* node_out) 
     SEM_HIP(c, upload(c, c->rec_b, b));
     SEM_HIP(c, upload(c, c->rec_loc, loc.empty() ? std::vector<int32_t>{0} : loc));
     SEM_HIP(c, upload(c, c->rec_idx, idx.empty() ? std::vector<int32_t>{0} : idx));
+    SEM_HIP(c, upload(c, c->rec_node, node.empty() ? std::vector<int32_t>{0} : node));
     return SEM_OK;
 }
 
@@ -812,9 +863,11 @@ int sem_create(const sem_mesh* mesh, const sem_options* opt, sem_ctx** out) {
         delete c;
         return SEM_ERR_INVALID_ARG;
     }
+    // AUTO: owner-tile LDS accumulation, measured fastest for every kernel (colour passes
+    // and global atomics both move r through L2 and HBM)
     c->scatter = opt->scatter == SEM_SCATTER_AUTO ? SEM_SCATTER_LDS_ATOMIC : opt->scatter;
-    if (c->scatter != SEM_SCATTER_LDS_ATOMIC) {
-        g_create_error = "this scatter is not available";
+    if (c->scatter != SEM_SCATTER_LDS_ATOMIC && (c->S != 1 || opt->formulation != SEM_FORM_LEAPFROG)) {
+        g_create_error = "the COLOUR and ATOMIC scatters run the single-shot leapfrog step (n_shots = 1)";
         delete c;
         return SEM_ERR_INVALID_ARG;
     }
@@ -878,6 +931,20 @@ int sem_create(const sem_mesh* mesh, const sem_options* opt, sem_ctx** out) {
         g_create_error = err;
         delete c;
         return code;
+    }
+    {
+        const sem::Plan& P = c->plan;
+        c->elem_slot.resize(P.ne);
+        std::iota(c->elem_slot.begin(), c->elem_slot.end(), 0);
+        c->ranges = {0, P.ne};
+        if (c->scatter == SEM_SCATTER_COLOUR) {
+            // colour classes one after another, each in the element (curve) order
+            std::stable_sort(c->elem_slot.begin(), c->elem_slot.end(),
+                             [&](int32_t x, int32_t y) { return P.colour[x] < P.colour[y]; });
+            c->ranges.assign(P.n_colours + 1, 0);
+            for (int64_t k = 0; k < P.ne; ++k) c->ranges[P.colour[k] + 1]++;
+            for (int32_t k = 0; k < P.n_colours; ++k) c->ranges[k + 1] += c->ranges[k];
+        }
     }
     c->setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (!c->host_only) {
@@ -957,6 +1024,9 @@ int sem_get_info(const sem_ctx* c, sem_info* info) {
     const double elem_words = row_kernel(c) ? 8.0
                               : 3.0 * nq + 1.0 + (shots_kernel(c) ? (P.p - 1.0) * (P.p - 1.0) : 0.0);
     info->kernel_bytes_per_step = (double)P.ne * (nq * 4.0 + elem_words * w) + per_node;
+    // global accumulator: every node's r written at least once by the element launches,
+    // then read and cleared by the node pass
+    if (c->scatter != SEM_SCATTER_LDS_ATOMIC) info->kernel_bytes_per_step += (double)P.nn * 3.0 * w;
     const double n = (double)P.n;
     info->alg_flops_per_step = (double)P.ne * c->S * (8.0 * n * n * n + 7.0 * n * n) +
                                (double)P.nn * c->S * 4.0;
@@ -1281,7 +1351,8 @@ void sem_destroy(sem_ctx* c) {
         DevBuf* bufs[] = {&c->conn, &c->G, &c->c2, &c->dtminv, &c->tile_eb, &c->tile_nb, &c->tile_ns, &c->halo_b,
                           &c->halo, &c->n2o_node, &c->n2o_elem, &c->u[0], &c->u[1], &c->v,
                           &c->src_b, &c->src_loc, &c->src_shot, &c->src_w, &c->rec_b, &c->rec_loc,
-                          &c->rec_idx, &c->u_next, &c->hv[0], &c->hv[1], &c->minv_w, &c->u_pred};
+                          &c->rec_idx, &c->u_next, &c->hv[0], &c->hv[1], &c->minv_w, &c->u_pred,
+                          &c->racc, &c->src_node, &c->rec_node};
         for (DevBuf* b : bufs) dev_free(*b);
     }
     delete c;

@@ -64,11 +64,36 @@ struct StepArgs {
     // gradient pairing: grad[e] += sum_s (Khat_e u_in_e) . (u_pair_e)
     const T* u_pair;
     double* grad;
+    // global accumulator (scatter COLOUR / ATOMIC, single shot): the elements
+    // [e_begin, e_begin + e_count) of the element arrays add c^2 Khat_e u_e into racc [N];
+    // point lists with new node ids (src_node aligned with src_w, rec_node with rec_idx)
+    T* racc;
+    int32_t e_begin, e_count;
+    const int32_t* src_node;
+    const int32_t* rec_node;
+    int32_t n_src_pts, n_rec_pts;
     // 1D GLL nodes, weights and derivative matrix D[i*(p+1) + j] = l_j'(xi_i)
     T xi[kMaxP + 1];
     T w[kMaxP + 1];
     T D[(kMaxP + 1) * (kMaxP + 1)];
 };
+
+// Global-accumulator scatter (single shot, row-lane layout, elements in the order of the
+// element arrays): one launch adds c^2 Khat_e u_e of the elements [e_begin, e_begin + e_count)
+// into racc, with global floating-point atomics (atomic = true) or plain read-modify-write
+// (atomic = false: no two elements of the range may share a node, e.g. one colour class);
+// element-interior nodes take plain stores. With a.grad, also grad[e] += (Khat_e u_e).u_pair_e.
+template <typename T>
+hipError_t launch_elems(int p, int threads, bool atomic, const StepArgs<T>& a, hipStream_t stream);
+// Node pass after the element launches, over all n nodes: r = racc, racc = 0, then
+// mode 0: v -= dt M^-1 r, u_out = u_in + dt v; mode 1: r_out = r; mode 2: r_out = dt M^-1 r.
+template <typename T>
+hipError_t launch_node_update(const StepArgs<T>& a, int64_t n, hipStream_t stream);
+// Point terms of the global-accumulator step. phase 0 (before the element launches):
+// racc -= source amplitudes at src_node (shot a.shot) and adjoint injections at rec_node;
+// phase 1 (after the node pass): traces from u_out at rec_node.
+template <typename T>
+hipError_t launch_global_points(const StepArgs<T>& a, int phase, hipStream_t stream);
 
 // geo = threads * 8 + passes (threads 256/512/1024, passes 1/2/4 batched per round of
 // loads): single-shot row kernel, geometric factors computed in-kernel (shot_lanes 1);
@@ -105,10 +130,9 @@ hipError_t launch_grad_to_original(const double* acc, double* out, const int32_t
 // nodes of an element (Eq. v_change, F = I); R = -sum w detJ V . grad N (Eq. u_change_r_effic,
 // B = -I) summed into the owned nodes; U-dot = M-bar^{-1} (R + y(src_t)) (Eq. u_change).
 //   predictor (mode 0): U~ = U^n + h U-dot(V^n) into u_out; V~ is not stored.
-//   corrector (mode 1): V~ = V^n + h grad U^n formed in registers,
+//   fused corrector (mode 2): V~ = V^n + h grad U^n formed in registers,
 //     V^{n+1} = V^n + h/2 (grad U^n + grad U~) into v_out,
-//     U^{n+1} = (U^n + U~) / 2 + h/2 U-dot(V~) into u_out.
-//   fused corrector (mode 2): the corrector, and the next step's predictor
+//     U^{n+1} = (U^n + U~) / 2 + h/2 U-dot(V~) into u_out, and the next step's predictor
 //     U~ = U^{n+1} + h U-dot(V^{n+1}) into u_pred (V^{n+1} formed for halo elements too).
 // V is element-local, [E][2][nq] (element, component, local node). 512 threads, p+1 lanes
 // per element.

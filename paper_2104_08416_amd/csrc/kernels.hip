@@ -147,7 +147,7 @@ __device__ __forceinline__ T group_sum(T v) {
 __device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double recip(double x) { return 1.0 / x; }
 
-template <typename T, int P, int SL, int GEO>
+template <typename T, int P, int SL>
 __global__ void __launch_bounds__(kBlock, sizeof(T) == 8 ? SEM_MIN_WAVES_F64 : SEM_MIN_WAVES_F32) step_kernel(const StepArgs<T> a) {
     constexpr int N = P + 1, NQ = N * N;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -182,7 +182,7 @@ __global__ void __launch_bounds__(kBlock, sizeof(T) == 8 ? SEM_MIN_WAVES_F64 : S
         const int e = own ? eb + k : a.halo[hb + k - n_own_el];
         // element-blocked layouts: [E/64][component][q][64]; one byte offset per thread
         const uint32_t eoff = (uint32_t)((e >> 6) * (NQ * 64) + (e & 63)) * 4u;
-        const uint32_t goff = (uint32_t)((e >> 6) * ((GEO ? 6 : 3 * NQ) * 64) + (e & 63)) * (uint32_t)sizeof(T);
+        const uint32_t goff = (uint32_t)((e >> 6) * (3 * NQ * 64) + (e & 63)) * (uint32_t)sizeof(T);
         const uint32_t soff = (uint32_t)(s0 + s) * (uint32_t)sizeof(T);
         T u[NQ];
 #pragma unroll
@@ -196,11 +196,6 @@ __global__ void __launch_bounds__(kBlock, sizeof(T) == 8 ? SEM_MIN_WAVES_F64 : S
         //   r[a, j] += sum_i D[i, a] f1[i, j]   (first-axis flux of row j is complete)
         //   r[a, b] += D[j, b] f2[a, j]          (second-axis flux summed over rows)
         // so only u, r and one row of flux are live.
-        T bl[GEO ? 6 : 1];
-        if constexpr (GEO) {
-#pragma unroll
-            for (int c = 0; c < 6; ++c) bl[c] = bload<T>(r_G, goff + c * 64 * (uint32_t)sizeof(T));
-        }
         T r[NQ];
 #pragma unroll
         for (int q = 0; q < NQ; ++q) r[q] = T(0);
@@ -216,23 +211,9 @@ __global__ void __launch_bounds__(kBlock, sizeof(T) == 8 ? SEM_MIN_WAVES_F64 : S
                     gy += a.D[j * N + m] * u[i + N * m];
                 }
                 const int q = i + N * j;
-                T g11, g12, g22;
-                if constexpr (GEO) {
-                    // Jacobian of the bilinear map at (xi_i, xi_j), then
-                    // G = w_i w_j detJ J^-1 J^-T
-                    const T xs = bl[0] + bl[2] * a.xi[j];
-                    const T xt = bl[1] + bl[2] * a.xi[i];
-                    const T ys = bl[3] + bl[5] * a.xi[j];
-                    const T yt = bl[4] + bl[5] * a.xi[i];
-                    const T sc = (a.w[i] * a.w[j]) * recip(xs * yt - xt * ys);
-                    g11 = sc * (xt * xt + yt * yt);
-                    g12 = -sc * (xs * xt + ys * yt);
-                    g22 = sc * (xs * xs + ys * ys);
-                } else {
-                    g11 = bload<T>(r_G, goff + q * 64 * (uint32_t)sizeof(T));
-                    g12 = bload<T>(r_G, goff + (NQ + q) * 64 * (uint32_t)sizeof(T));
-                    g22 = bload<T>(r_G, goff + (2 * NQ + q) * 64 * (uint32_t)sizeof(T));
-                }
+                const T g11 = bload<T>(r_G, goff + q * 64 * (uint32_t)sizeof(T));
+                const T g12 = bload<T>(r_G, goff + (NQ + q) * 64 * (uint32_t)sizeof(T));
+                const T g22 = bload<T>(r_G, goff + (2 * NQ + q) * 64 * (uint32_t)sizeof(T));
                 f1[i] = g11 * gx + g12 * gy;
                 f2[i] = g12 * gx + g22 * gy;
             }
@@ -631,6 +612,105 @@ __global__ void __launch_bounds__(BT) step_shots_kernel(const StepArgs<T> a) {
 // per-element LDS stage written and read by the same wave (LDS executes one wave's
 // instructions in order, so no barrier is needed). Geometric factors come from the six
 // bilinear-map coefficients of the element.
+// Row-lane layout (single shot): p+1 consecutive lanes of a wave hold the p+1 rows (second
+// reference index j) of one element, and the element's LDS stage `st` [nq] is written and read
+// by those lanes only. A wave barrier orders every stage exchange: it keeps the compiler from
+// moving LDS accesses across it, and the lanes of one wave execute LDS instructions in order.
+__device__ __forceinline__ void wave_sync() { __builtin_amdgcn_wave_barrier(); }
+
+// Row j of D, column j of D, xi_j and w_j in registers, selected from the uniform kernel
+// arguments (no per-lane memory reads).
+template <typename T, int P, typename Args>
+__device__ __forceinline__ void row_constants(const Args& a, int j, T (&Dj)[P + 1], T (&DjT)[P + 1], T& xij,
+                                              T& wj) {
+    constexpr int N = P + 1;
+    xij = a.xi[0];
+    wj = a.w[0];
+#pragma unroll
+    for (int m = 0; m < N; ++m) {
+        Dj[m] = a.D[m];
+        DjT[m] = a.D[m * N];
+    }
+#pragma unroll
+    for (int jj = 1; jj < N; ++jj) {
+        if (j == jj) {
+#pragma unroll
+            for (int m = 0; m < N; ++m) {
+                Dj[m] = a.D[jj * N + m];
+                DjT[m] = a.D[m * N + jj];
+            }
+            xij = a.xi[jj];
+            wj = a.w[jj];
+        }
+    }
+}
+
+// Stiffness apply of row j of one element (Eqs. deriv_u and R, second-order flux, without
+// c^2): from u[i] = u(xi_i, xi_j) and the element's bilinear-map coefficients bl[0..5]
+// (x_xi = bl0 + bl2 eta, x_eta = bl1 + bl2 xi, y likewise with bl3..5), r[a] = (Khat_e u)(a, j).
+// The reference gradient along the row comes from u, across rows from the stage; the
+// geometric factors w_i w_j detJ J^-1 J^-T are formed at each point; D^T along the row stays
+// in registers, across rows it goes through the stage again.
+template <typename T, int P, typename Args>
+__device__ __forceinline__ void row_stiffness(const Args& a, const T (&u)[P + 1], const T* bl, T* st, int j,
+                                              const T (&Dj)[P + 1], const T (&DjT)[P + 1], T xij, T wj,
+                                              T (&r)[P + 1]) {
+    constexpr int N = P + 1;
+#pragma unroll
+    for (int i = 0; i < N; ++i) st[i + N * j] = u[i];
+    wave_sync();
+    T gx[N], gy[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        T sacc = T(0);
+#pragma unroll
+        for (int m = 0; m < N; ++m) sacc += a.D[i * N + m] * u[m];
+        gx[i] = sacc;
+        gy[i] = T(0);
+    }
+#pragma unroll
+    for (int m = 0; m < N; ++m) {
+        const T djm = Dj[m];
+#pragma unroll
+        for (int i = 0; i < N; ++i) gy[i] += djm * st[i + N * m];
+    }
+    // geometric flux at (xi_i, xi_j); first-axis D^T stays in the row
+    const T xs = bl[0] + bl[2] * xij;
+    const T ys = bl[3] + bl[5] * xij;
+    T f2[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        const T xt = bl[1] + bl[2] * a.xi[i];
+        const T yt = bl[4] + bl[5] * a.xi[i];
+        const T sc = (a.w[i] * wj) * recip(xs * yt - xt * ys);
+        const T g11 = sc * (xt * xt + yt * yt);
+        const T g12 = -sc * (xs * xt + ys * yt);
+        const T g22 = sc * (xs * xs + ys * ys);
+        const T f1 = g11 * gx[i] + g12 * gy[i];
+        f2[i] = g12 * gx[i] + g22 * gy[i];
+        gx[i] = f1;
+    }
+#pragma unroll
+    for (int aa = 0; aa < N; ++aa) {
+        T sacc = T(0);
+#pragma unroll
+        for (int i = 0; i < N; ++i) sacc += a.D[i * N + aa] * gx[i];
+        r[aa] = sacc;
+    }
+    // second-axis D^T across rows: r[a, j] += sum_m D[m, j] f2[a, m]
+    wave_sync();                                       // every lane has read the u rows
+#pragma unroll
+    for (int i = 0; i < N; ++i) st[i + N * j] = f2[i];
+    wave_sync();
+#pragma unroll
+    for (int m = 0; m < N; ++m) {
+        const T dmj = DjT[m];
+#pragma unroll
+        for (int aa = 0; aa < N; ++aa) r[aa] += dmj * st[aa + N * m];
+    }
+    wave_sync();                                       // before the stage is written again
+}
+
 template <typename T, int P, int NP>
 constexpr int rows_waves() {
     // FP32 p <= 4: eight waves (64 VGPRs); p >= 5 is faster left to the compiler (the graded
@@ -691,26 +771,8 @@ step_rows_kernel(const StepArgs<T> a) {
     const int j = lane - kw * N;                       // row of that element
     const int slot = wave * EPW + kw;
     T* st = stage + slot * NQP;
-    // The row j of a thread never changes: keep row j and column j of D, xi_j and w_j in
-    // registers (selected from the uniform kernel arguments, no per-lane memory reads).
-    T Dj[N], DjT[N], xij = a.xi[0], wj = a.w[0];
-#pragma unroll
-    for (int m = 0; m < N; ++m) {
-        Dj[m] = a.D[m];
-        DjT[m] = a.D[m * N];
-    }
-#pragma unroll
-    for (int jj = 1; jj < N; ++jj) {
-        if (j == jj) {
-#pragma unroll
-            for (int m = 0; m < N; ++m) {
-                Dj[m] = a.D[jj * N + m];
-                DjT[m] = a.D[m * N + jj];
-            }
-            xij = a.xi[jj];
-            wj = a.w[jj];
-        }
-    }
+    T Dj[N], DjT[N], xij, wj;
+    row_constants<T, P>(a, j, Dj, DjT, xij, wj);
     // NP passes at a time: every pass's indices and geometry are requested first, then
     // every pass's gathers, so a tile costs two memory round trips instead of 2 NP.
     for (int base = 0; base < n_items; base += NP * EPB) {
@@ -747,57 +809,8 @@ step_rows_kernel(const StepArgs<T> a) {
             if (!act[pp]) continue;
             const int k = base + pp * EPB + slot;
             const bool own = k < n_own_el;
-            const int e = es[pp];
-#pragma unroll
-            for (int i = 0; i < N; ++i) st[i + N * j] = u[pp][i];
-            // reference gradient at the row's points: d/dxi from the row, d/deta from the stage
-            T gx[N], gy[N];
-#pragma unroll
-            for (int i = 0; i < N; ++i) {
-                T sacc = T(0);
-#pragma unroll
-                for (int m = 0; m < N; ++m) sacc += a.D[i * N + m] * u[pp][m];
-                gx[i] = sacc;
-                gy[i] = T(0);
-            }
-#pragma unroll
-            for (int m = 0; m < N; ++m) {
-                const T djm = Dj[m];
-#pragma unroll
-                for (int i = 0; i < N; ++i) gy[i] += djm * st[i + N * m];
-            }
-            // geometric flux at (xi_i, xi_j); first-axis D^T stays in the row
-            const T xs = bl[pp][0] + bl[pp][2] * xij;
-            const T ys = bl[pp][3] + bl[pp][5] * xij;
-            T f2[N], r[N];
-#pragma unroll
-            for (int i = 0; i < N; ++i) {
-                const T xt = bl[pp][1] + bl[pp][2] * a.xi[i];
-                const T yt = bl[pp][4] + bl[pp][5] * a.xi[i];
-                const T sc = (a.w[i] * wj) * recip(xs * yt - xt * ys);
-                const T g11 = sc * (xt * xt + yt * yt);
-                const T g12 = -sc * (xs * xt + ys * yt);
-                const T g22 = sc * (xs * xs + ys * ys);
-                const T f1 = g11 * gx[i] + g12 * gy[i];
-                f2[i] = g12 * gx[i] + g22 * gy[i];
-                gx[i] = f1;
-            }
-#pragma unroll
-            for (int aa = 0; aa < N; ++aa) {
-                T sacc = T(0);
-#pragma unroll
-                for (int i = 0; i < N; ++i) sacc += a.D[i * N + aa] * gx[i];
-                r[aa] = sacc;
-            }
-            // second-axis D^T across rows: r[a, j] += sum_m D[m, j] f2[a, m]
-#pragma unroll
-            for (int i = 0; i < N; ++i) st[i + N * j] = f2[i];
-#pragma unroll
-            for (int m = 0; m < N; ++m) {
-                const T dmj = DjT[m];
-#pragma unroll
-                for (int aa = 0; aa < N; ++aa) r[aa] += dmj * st[aa + N * m];
-            }
+            T r[N];
+            row_stiffness<T, P>(a, u[pp], bl[pp], st, j, Dj, DjT, xij, wj, r);
             if constexpr (GRAD) {
                 if (own) {
                     T dot = T(0);
@@ -806,14 +819,6 @@ step_rows_kernel(const StepArgs<T> a) {
                         dot += r[aa] * bload<T>(r_pair, (uint32_t)idx[pp][aa] * (uint32_t)sizeof(T));
                     dots[pp] = dot;
                 }
-            } else if (a.grad != nullptr && own) {
-                // not reached (forward launches carry no gradient); kept so that the forward
-                // instantiation compiles to the register allocation it was tuned with
-                T dot = T(0);
-#pragma unroll
-                for (int aa = 0; aa < N; ++aa)
-                    dot += r[aa] * bload<T>(r_pair, (uint32_t)idx[pp][aa] * (uint32_t)sizeof(T));
-                atomicAdd(&a.grad[e], (double)dot);
             }
             // Element-interior nodes (0 < a, j < p) belong to this element alone: a plain
             // LDS store; nodes on element edges and corners are shared and need atomics.
@@ -884,9 +889,117 @@ step_rows_kernel(const StepArgs<T> a) {
     }
 }
 
-template <typename T, int P, int SL, int GEO>
+// ---------------------------------------------------------------------------------------
+// Global accumulator (SEM_SCATTER_COLOUR and SEM_SCATTER_ATOMIC): the paper's structure of a
+// step (Alg. 2 then the update): every element adds its contribution into a global r, then a
+// node pass applies the update. Single shot, row-lane layout of step_rows_kernel, one
+// workgroup per 64 / (p+1) * RB / 64 consecutive elements of the launch range, XCD-aware.
+template <typename T, int P, int RB, bool ATOMIC, bool GRAD>
+__global__ void __attribute__((amdgpu_flat_work_group_size(RB, RB))) elem_rows_kernel(const StepArgs<T> a) {
+    constexpr int N = P + 1, NQ = N * N;
+    constexpr int NQP = (NQ + 3) & ~3;
+    constexpr int EPW = 64 / N;
+    constexpr int EPB = EPW * (RB / 64);
+    __shared__ __align__(16) T stage[EPB * NQP];
+    const int blk = xcd_logical_block();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int kw = lane / N, j = lane - kw * N;
+    const int slot = wave * EPW + kw;
+    const int k = blk * EPB + slot;
+    // all p+1 lanes of an element leave together, so the stage exchange stays intact
+    if (kw >= EPW || k >= a.e_count) return;
+    const int e = a.e_begin + k;
+    T* st = stage + slot * NQP;
+    T Dj[N], DjT[N], xij, wj;
+    row_constants<T, P>(a, j, Dj, DjT, xij, wj);
+    const rsrc_t r_conn = make_rsrc(a.conn, a.conn_bytes);
+    const rsrc_t r_G = make_rsrc(a.G, a.G_bytes);
+    const rsrc_t r_u = make_rsrc(a.u_in, a.state_bytes);
+    int idx[N];
+    load_ids<N>(r_conn, (uint32_t)(e * NQ + N * j) * 4u, idx);
+    T bl[8];
+    load_rec8(r_G, (uint32_t)e * 8u * (uint32_t)sizeof(T), bl);
+    T u[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) u[i] = bload<T>(r_u, (uint32_t)idx[i] * (uint32_t)sizeof(T));
+    T r[N];
+    row_stiffness<T, P>(a, u, bl, st, j, Dj, DjT, xij, wj, r);
+    if constexpr (GRAD) {
+        const rsrc_t r_pair = make_rsrc(a.u_pair, a.state_bytes);
+        T dot = T(0);
+#pragma unroll
+        for (int aa = 0; aa < N; ++aa) dot += r[aa] * bload<T>(r_pair, (uint32_t)idx[aa] * (uint32_t)sizeof(T));
+        T tot = T(0);
+#pragma unroll
+        for (int m = 0; m < N; ++m) tot += __shfl(dot, kw * N + m, 64);
+        if (j == 0) atomicAdd(&a.grad[e], (double)tot);
+    }
+    // element-interior nodes (0 < a, j < p) belong to this element alone: plain stores
+    const bool inner_row = j > 0 && j < P;
+#pragma unroll
+    for (int aa = 0; aa < N; ++aa) {
+        const T val = bl[6] * r[aa];
+        T* dst = a.racc + idx[aa];
+        if (aa > 0 && aa < P && inner_row) *dst = val;
+        else if constexpr (ATOMIC) atomicAdd(dst, val);
+        else *dst += val;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) node_update_kernel(const StepArgs<T> a, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const T r = a.racc[i];
+        a.racc[i] = T(0);
+        if (a.mode == 0) {
+            const T vn = a.v[i] - a.dtminv[i] * r;
+            a.v[i] = vn;
+            a.u_out[i] = a.u_in[i] + a.dt * vn;
+        } else {
+            a.r_out[i] = a.mode == 2 ? a.dtminv[i] * r : r;
+        }
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) global_points_kernel(const StepArgs<T> a, int phase) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (phase == 0) {
+        if (a.src_node != nullptr && i < a.n_src_pts && a.src_shot[i] == a.shot)
+            atomicAdd(&a.racc[a.src_node[i]], -(a.src_w[i] * (T)ricker(a.src_t, a.f0, a.t0)));
+        if (a.inj != nullptr && i < a.n_rec_pts)
+            atomicAdd(&a.racc[a.rec_node[i]],
+                      -(a.inj[(int64_t)a.rec_idx[i] * a.inj_cols + a.inj_col] * a.inj_scale));
+    } else if (a.trace != nullptr && i < a.n_rec_pts) {
+        a.trace[(int64_t)a.rec_idx[i] * a.trace_cols + a.trace_col] = a.u_out[a.rec_node[i]];
+    }
+}
+
+template <typename T, int P, int RB>
+hipError_t launch_elems_p(bool atomic, const StepArgs<T>& a, hipStream_t st) {
+    constexpr int EPB = (64 / (P + 1)) * (RB / 64);
+    if (a.e_count <= 0) return hipSuccess;
+    const unsigned blocks = (unsigned)((a.e_count + EPB - 1) / EPB);
+    auto fn = atomic ? (a.grad ? elem_rows_kernel<T, P, RB, true, true> : elem_rows_kernel<T, P, RB, true, false>)
+                     : (a.grad ? elem_rows_kernel<T, P, RB, false, true> : elem_rows_kernel<T, P, RB, false, false>);
+    hipLaunchKernelGGL(fn, dim3(blocks), dim3(RB), 0, st, a);
+    return hipGetLastError();
+}
+
+template <typename T, int P>
+hipError_t launch_elems_t(int threads, bool atomic, const StepArgs<T>& a, hipStream_t st) {
+    switch (threads) {
+        case 256: return launch_elems_p<T, P, 256>(atomic, a, st);
+        case 512: return launch_elems_p<T, P, 512>(atomic, a, st);
+        case 1024: return launch_elems_p<T, P, 1024>(atomic, a, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T, int P, int SL>
 hipError_t launch_one(int64_t n_tiles, size_t lds, const StepArgs<T>& a, hipStream_t st) {
-    auto fn = step_kernel<T, P, SL, GEO>;
+    auto fn = step_kernel<T, P, SL>;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -947,25 +1060,27 @@ hipError_t launch_p(int sl, int geo, int64_t nt, size_t lds, const StepArgs<T>& 
         }
     }
     switch (sl) {
-        case 1: return launch_one<T, P, 1, 0>(nt, lds, a, st);
-        case 2: return launch_one<T, P, 2, 0>(nt, lds, a, st);
-        case 4: return launch_one<T, P, 4, 0>(nt, lds, a, st);
-        case 8: return launch_one<T, P, 8, 0>(nt, lds, a, st);
-        case 16: return launch_one<T, P, 16, 0>(nt, lds, a, st);
-        case 32: return launch_one<T, P, 32, 0>(nt, lds, a, st);
+        case 1: return launch_one<T, P, 1>(nt, lds, a, st);
+        case 2: return launch_one<T, P, 2>(nt, lds, a, st);
+        case 4: return launch_one<T, P, 4>(nt, lds, a, st);
+        case 8: return launch_one<T, P, 8>(nt, lds, a, st);
+        case 16: return launch_one<T, P, 16>(nt, lds, a, st);
+        case 32: return launch_one<T, P, 32>(nt, lds, a, st);
         default: return hipErrorInvalidValue;
     }
 }
 
 // ---------------------------------------------------------------------------------------
-// First-order u-v system with Heun's scheme, one launch per stage. At GLL point (i, j) of an
+// First-order u-v system with Heun's scheme, one launch per step. At GLL point (i, j) of an
 // element the reference derivatives of u give grad u = J^-T (d/dxi, d/deta) u (V-dot,
 // Eq. v_change), and V enters R through A_xi = w_i w_j (Vx y_eta - Vy x_eta),
 // A_eta = w_i w_j (Vy x_xi - Vx y_xi) (det J cancels): R(a, b) -= D(i, a) A_xi(i, b) and
 // D(j, b) A_eta(a, j). R is summed into the tile's owned nodes in FP64 LDS words; the owned
 // nodes then take their new U.
-//   predictor (CORR = false): R(V^n); U~ = U^n + h M-bar^-1 (R + y(t_n)). V~ is not stored.
-//   corrector (CORR = true): V~ = V^n + h grad U^n is formed again in registers for every
+// Two instantiations: the predictor (CORR = FUSE = false), run only when the context holds no
+// prediction for the current state, and the fused corrector (CORR = FUSE = true), once per step.
+//   predictor: R(V^n); U~ = U^n + h M-bar^-1 (R + y(t_n)). V~ is not stored.
+//   corrector (CORR): V~ = V^n + h grad U^n is formed again in registers for every
 //     element the tile touches (its flux needs it); own elements write
 //     V^{n+1} = V^n + h/2 (grad U^n + grad U~); R(V~);
 //     U^{n+1} = U^n / 2 + U~ / 2 + h/2 M-bar^-1 (R + y(t_{n+1})).
@@ -1065,14 +1180,17 @@ __global__ void __launch_bounds__(kRowBlock / 2) heun_rows_kernel(const HeunArgs
                 for (int aa = 0; aa < N; ++aa) r[aa] -= a.D[i * N + aa] * axi;
             }
             // across rows: R(aa, j) -= sum_m D(m, j) A_eta(aa, m), A_eta exchanged via the stage
+            wave_sync();                               // earlier reads of the stage are done
 #pragma unroll
             for (int i = 0; i < N; ++i) st[i + N * j] = aeta[i];
+            wave_sync();
 #pragma unroll
             for (int m = 0; m < N; ++m) {
                 const T dmj = a.D[m * N + j];
 #pragma unroll
                 for (int aa = 0; aa < N; ++aa) r[aa] -= dmj * st[aa + N * m];
             }
+            wave_sync();                               // before the stage is written again
             const bool inner_row = j > 0 && j < P;
 #pragma unroll
             for (int aa = 0; aa < N; ++aa) {
@@ -1100,8 +1218,10 @@ __global__ void __launch_bounds__(kRowBlock / 2) heun_rows_kernel(const HeunArgs
             T u[N], nx[N], ny[N];
 #pragma unroll
             for (int i = 0; i < N; ++i) u[i] = bload<T>(r_u0, (uint32_t)idx[i] * (uint32_t)sizeof(T));
+            wave_sync();
 #pragma unroll
             for (int i = 0; i < N; ++i) st[i + N * j] = u[i];
+            wave_sync();
 #pragma unroll
             for (int i = 0; i < N; ++i) {
                 T dx, dy;
@@ -1114,8 +1234,10 @@ __global__ void __launch_bounds__(kRowBlock / 2) heun_rows_kernel(const HeunArgs
             if (FUSE || own) {
 #pragma unroll
                 for (int i = 0; i < N; ++i) u[i] = bload<T>(r_u1, (uint32_t)idx[i] * (uint32_t)sizeof(T));
+                wave_sync();
 #pragma unroll
                 for (int i = 0; i < N; ++i) st[i + N * j] = u[i];
+                wave_sync();
 #pragma unroll
                 for (int i = 0; i < N; ++i) {
                     T dx, dy;
@@ -1176,8 +1298,8 @@ __global__ void __launch_bounds__(kRowBlock / 2) heun_rows_kernel(const HeunArgs
 template <typename T, int P>
 hipError_t launch_heun_p(int mode, int64_t n_tiles, size_t lds, const HeunArgs<T>& a, hipStream_t st) {
     constexpr int RB = kRowBlock / 2;
-    auto fn = mode == 2 ? heun_rows_kernel<T, P, true, true>
-              : (mode == 1 ? heun_rows_kernel<T, P, true, false> : heun_rows_kernel<T, P, false, false>);
+    if (mode != 0 && mode != 2) return hipErrorInvalidValue;
+    auto fn = mode == 2 ? heun_rows_kernel<T, P, true, true> : heun_rows_kernel<T, P, false, false>;
     lds = heun_lds_bytes(P, mode, a.lds_own, sizeof(T));
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
@@ -1276,6 +1398,37 @@ hipError_t launch_step(int p, int sl, int geo, int64_t nt, size_t lds, const Ste
 }
 
 template <typename T>
+hipError_t launch_elems(int p, int threads, bool atomic, const StepArgs<T>& a, hipStream_t st) {
+    switch (p) {
+        case 1: return launch_elems_t<T, 1>(threads, atomic, a, st);
+        case 2: return launch_elems_t<T, 2>(threads, atomic, a, st);
+        case 3: return launch_elems_t<T, 3>(threads, atomic, a, st);
+        case 4: return launch_elems_t<T, 4>(threads, atomic, a, st);
+        case 5: return launch_elems_t<T, 5>(threads, atomic, a, st);
+        case 6: return launch_elems_t<T, 6>(threads, atomic, a, st);
+        case 7: return launch_elems_t<T, 7>(threads, atomic, a, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+hipError_t launch_node_update(const StepArgs<T>& a, int64_t n, hipStream_t st) {
+    const int64_t b = (n + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(node_update_kernel<T>, dim3((unsigned)(b < 1 ? 1 : (b > 65536 ? 65536 : b))), dim3(kBlock), 0,
+                       st, a, n);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_global_points(const StepArgs<T>& a, int phase, hipStream_t st) {
+    const int n = phase == 0 ? (a.n_src_pts > a.n_rec_pts ? a.n_src_pts : a.n_rec_pts) : a.n_rec_pts;
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(global_points_kernel<T>, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, a,
+                       phase);
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_nodes_to_original(const T* in, T* out, const int32_t* n2o, int64_t N, int32_t S,
                                     bool shot_major, hipStream_t st) {
     hipLaunchKernelGGL(to_original_kernel<T>, dim3(grid_for(N * S)), dim3(kBlock), 0, st, in, out, n2o, N, S,
@@ -1339,7 +1492,10 @@ hipError_t launch_heun_stage(int p, int mode, int64_t nt, size_t lds, const Heun
     template hipError_t launch_fill<T>(T*, T, int64_t, hipStream_t);                              \
     template hipError_t launch_scale<T>(T*, double, int64_t, hipStream_t);                        \
     template hipError_t launch_sumsq<T>(const T*, int64_t, double*, hipStream_t);                 \
-    template hipError_t launch_heun_stage<T>(int, int, int64_t, size_t, const HeunArgs<T>&, hipStream_t);
+    template hipError_t launch_heun_stage<T>(int, int, int64_t, size_t, const HeunArgs<T>&, hipStream_t); \
+    template hipError_t launch_elems<T>(int, int, bool, const StepArgs<T>&, hipStream_t);         \
+    template hipError_t launch_node_update<T>(const StepArgs<T>&, int64_t, hipStream_t);          \
+    template hipError_t launch_global_points<T>(const StepArgs<T>&, int, hipStream_t);
 
 SEM_INSTANTIATE(float)
 SEM_INSTANTIATE(double)

@@ -115,14 +115,47 @@ def test_apply_stiffness_fp32_64_shots(semlib, gpu_ok):
     assert rel(r, r_o) <= 2e-6
 
 
-def test_fp32_1000_steps(semlib, gpu_ok):
-    """FP32 state and arithmetic against the FP64 oracle after 1000 steps."""
-    say("case layered64 fp32 1000 steps")
+@pytest.mark.parametrize("scatter", ["auto", "colour", "atomic"])
+def test_fp32_1000_steps(semlib, gpu_ok, scatter):
+    """FP32 state and arithmetic against the FP64 oracle after 1000 steps, with each way of
+    summing the element contributions (owner-tile LDS, colour passes, global atomics)."""
+    say("case layered64 fp32 1000 steps", scatter)
     wl = workloads.workload("layered1024", n=64, nsteps=1000)
-    (tr, u, v), (tr_o, u_o, v_o) = run_both(semlib, wl, wl.nsteps, "f32", "hilbert")
+    (tr, u, v), (tr_o, u_o, v_o) = run_both(semlib, wl, wl.nsteps, "f32", "hilbert", scatter=scatter)
     err = rel(u, u_o)
-    say("fp32 rel L2 after 1000 steps", err)
+    say("fp32 rel L2 after 1000 steps", scatter, err)
     assert err <= 1e-5
+
+
+@pytest.mark.parametrize("scatter", ["colour", "atomic"])
+@pytest.mark.parametrize("order", ["hilbert", "random", "lex"])
+def test_fp64_global_scatter(semlib, gpu_ok, scatter, order):
+    """The paper's colour passes (Sec. 5, Alg. 2) and the global-atomic scatter, FP64, 30 x 30
+    jittered layered mesh, source and receivers, 400 steps: <= 1e-12 against the oracle."""
+    say("case layered30 fp64 scatter", scatter, order)
+    wl = workloads.workload("layered1024", n=30, nsteps=400)
+    wl.src_xy = np.array([[5000.0, 8000.0]])
+    (tr, u, v), (tr_o, u_o, v_o) = run_both(semlib, wl, wl.nsteps, "f64", order, scatter=scatter)
+    assert rel(u, u_o) <= 1e-12
+    assert rel(v, v_o) <= 1e-12
+    assert rel(tr, tr_o) <= 1e-12
+    s = semlib.Simulator(wl.vxy, wl.quads, wl.c2, wl.p, precision="f64", order=order, scatter=scatter)
+    inf = s.info()
+    assert inf["scatter"] == semlib.SCATTERS[scatter] and inf["n_colours"] >= 4
+    s.close()
+
+
+@pytest.mark.parametrize("scatter", ["colour", "atomic"])
+def test_apply_stiffness_fp64_global_scatter(semlib, gpu_ok, scatter):
+    import torch
+    say("case apply fp64", scatter)
+    wl = workloads.workload("layered1024", n=40)
+    o = solver.SEM(wl.vxy, wl.quads, wl.c2, wl.p)
+    s = semlib.Simulator(wl.vxy, wl.quads, wl.c2, wl.p, precision="f64", scatter=scatter)
+    x = workloads.random_field(o.n_nodes, 1, seed=3)
+    r = s.apply_stiffness(torch.tensor(x, device="cuda")).cpu().numpy()
+    assert rel(r, (o.K @ x.T).T) <= 1e-13
+    s.close()
 
 
 def test_apply_stiffness_fp64(semlib, gpu_ok):
@@ -208,6 +241,18 @@ def test_adjoint_gradient_fp64_matches_oracle(semlib, gpu_ok, ckpt):
     J = 0.5 * float((res.double() ** 2).sum())
     assert J == pytest.approx(d["J"], rel=1e-11)
     g = s.adjoint_gradient(res.contiguous(), d["nsteps"], ckpt).cpu().numpy()
+    assert rel(g, d["g"]) <= 1e-10
+
+
+@pytest.mark.parametrize("scatter", ["colour", "atomic"])
+def test_adjoint_gradient_fp64_global_scatter(semlib, gpu_ok, scatter):
+    """Gradient pairing inside the element launches of the colour and atomic scatters."""
+    import torch
+    say("case adjoint fp64", scatter)
+    o, s, d = _tiny_inversion(semlib, "f64", shots=1, scatter=scatter)
+    tr = s.run(d["nsteps"])
+    res = tr - torch.tensor(d["obs"], device="cuda")
+    g = s.adjoint_gradient(res.contiguous(), d["nsteps"], 30).cpu().numpy()
     assert rel(g, d["g"]) <= 1e-10
 
 

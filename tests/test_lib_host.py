@@ -225,3 +225,25 @@ def test_colours_bit_exact(semlib, name, kw, orders):
         np.testing.assert_array_equal(got, want, err_msg=kind)
         assert s.info()["n_colours"] == int(want.max()) + 1
         s.close()
+
+
+def test_scatter_options(semlib):
+    """The scatter option: AUTO resolves to the owner-tile LDS scatter; COLOUR and ATOMIC are
+    single-shot leapfrog only; unknown values are refused."""
+    wl = workloads.workload("layered1024", n=12)
+    s = semlib.Simulator(wl.vxy, wl.quads, wl.c2, wl.p, device=-1)
+    assert s.info()["scatter"] == semlib.SCATTERS["lds_atomic"]
+    s.close()
+    s = semlib.Simulator(wl.vxy, wl.quads, wl.c2, wl.p, device=-1, scatter="colour")
+    assert s.info()["scatter"] == semlib.SCATTERS["colour"]
+    s.close()
+    for kw in (dict(scatter="colour", n_shots=2), dict(scatter="atomic", formulation="heun")):
+        with pytest.raises(semlib.SemError) as ei:
+            semlib.Simulator(wl.vxy, wl.quads, wl.c2, wl.p, device=-1, **kw)
+        assert ei.value.status == "INVALID_ARG"
+    semlib.SCATTERS["bogus"] = 7
+    try:
+        with pytest.raises(semlib.SemError):
+            semlib.Simulator(wl.vxy, wl.quads, wl.c2, wl.p, device=-1, scatter="bogus")
+    finally:
+        del semlib.SCATTERS["bogus"]

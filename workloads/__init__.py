@@ -62,6 +62,7 @@ class Workload:
     orders: tuple = ("hilbert",)
     ckpt_every: int = 0
     c2_init: Optional[np.ndarray] = None   # starting model of the inversion workload
+    anomaly_xy: Optional[np.ndarray] = None  # centre of the inversion workload's anomaly
 
     @property
     def n_elements(self) -> int:
@@ -200,19 +201,27 @@ def workload(name: str, n: Optional[int] = None, nsteps: Optional[int] = None,
     if name == "adjoint512":
         # 512^2 jittered quads, p=4; true model = layers x (1 + 10% Gaussian anomaly), initial = layers;
         # 8 shots x 128 receivers, 1500 steps, checkpoints every 40 steps.
+        # In 1500 steps at the CFL-0.3 time step a wave travels about 200 m in the 1500 m/s top
+        # layer (~10 elements), so the shots, the anomaly and the receivers they illuminate sit
+        # within that reach: the anomaly 150 m below the top edge (sigma = L/64), the shots on
+        # a line 100 m below the top, 125 m apart, centred over it.
         nx = n or 512
         L = 10000.0
         S = n_shots or 8
         vxy, quads, xc, yc = grid_mesh(nx, nx, L, L, jitter=0.2)
         c0 = layered_c(yc, L)
-        sig = L / 16.0
-        bump = np.exp(-((xc - L / 2) ** 2 + (yc - L / 2) ** 2) / (2.0 * sig * sig))
+        sig = L / 64.0
+        anomaly = np.array([L / 2, L - 150.0])
+        bump = np.exp(-((xc - anomaly[0]) ** 2 + (yc - anomaly[1]) ** 2) / (2.0 * sig * sig))
         c_true = c0 * (1.0 + 0.1 * bump)
-        src = np.stack([(np.arange(S) + 0.5) * (L / S), np.full(S, L - L / 20.0)], axis=1)
-        return Workload(name, p or 4, nx, nx, L, L, vxy, quads, c_true * c_true,
-                        src, np.arange(S, dtype=np.int32), S, _top_receivers(L, L),
-                        15.0, nsteps or 1500, precision="f32", orders=("hilbert",),
-                        ckpt_every=40, c2_init=c0 * c0)
+        src = np.stack([L / 2 + (np.arange(S) - (S - 1) / 2.0) * (L / 80.0), np.full(S, L - L / 100.0)],
+                       axis=1)
+        wl = Workload(name, p or 4, nx, nx, L, L, vxy, quads, c_true * c_true,
+                      src, np.arange(S, dtype=np.int32), S, _top_receivers(L, L),
+                      15.0, nsteps or 1500, precision="f32", orders=("hilbert",),
+                      ckpt_every=40, c2_init=c0 * c0)
+        wl.anomaly_xy = anomaly
+        return wl
     raise KeyError(f"unknown workload {name!r}")
 
 
