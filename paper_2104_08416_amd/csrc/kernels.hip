@@ -646,7 +646,10 @@ __device__ __forceinline__ void row_constants(const Args& a, int j, T (&Dj)[P + 
 }
 
 // Stiffness apply of row j of one element (Eqs. deriv_u and R, second-order flux, without
-// c^2): from u[i] = u(xi_i, xi_j) and the element's bilinear-map coefficients bl[0..5]
+// c^2), as used by the global-accumulator kernel. step_rows_kernel carries the same
+// contraction written out in its own body: its FP32 allocation is tuned to 64 VGPRs, and the
+// scheduler spills inside the element loop when the code is arranged differently.
+// From u[i] = u(xi_i, xi_j) and the element's bilinear-map coefficients bl[0..5]
 // (x_xi = bl0 + bl2 eta, x_eta = bl1 + bl2 xi, y likewise with bl3..5), r[a] = (Khat_e u)(a, j).
 // The reference gradient along the row comes from u, across rows from the stage; the
 // geometric factors w_i w_j detJ J^-1 J^-T are formed at each point; D^T along the row stays
@@ -771,8 +774,26 @@ step_rows_kernel(const StepArgs<T> a) {
     const int j = lane - kw * N;                       // row of that element
     const int slot = wave * EPW + kw;
     T* st = stage + slot * NQP;
-    T Dj[N], DjT[N], xij, wj;
-    row_constants<T, P>(a, j, Dj, DjT, xij, wj);
+    // The row j of a thread never changes: keep row j and column j of D, xi_j and w_j in
+    // registers (selected from the uniform kernel arguments, no per-lane memory reads).
+    T Dj[N], DjT[N], xij = a.xi[0], wj = a.w[0];
+#pragma unroll
+    for (int m = 0; m < N; ++m) {
+        Dj[m] = a.D[m];
+        DjT[m] = a.D[m * N];
+    }
+#pragma unroll
+    for (int jj = 1; jj < N; ++jj) {
+        if (j == jj) {
+#pragma unroll
+            for (int m = 0; m < N; ++m) {
+                Dj[m] = a.D[jj * N + m];
+                DjT[m] = a.D[m * N + jj];
+            }
+            xij = a.xi[jj];
+            wj = a.w[jj];
+        }
+    }
     // NP passes at a time: every pass's indices and geometry are requested first, then
     // every pass's gathers, so a tile costs two memory round trips instead of 2 NP.
     for (int base = 0; base < n_items; base += NP * EPB) {
@@ -809,8 +830,61 @@ step_rows_kernel(const StepArgs<T> a) {
             if (!act[pp]) continue;
             const int k = base + pp * EPB + slot;
             const bool own = k < n_own_el;
-            T r[N];
-            row_stiffness<T, P>(a, u[pp], bl[pp], st, j, Dj, DjT, xij, wj, r);
+            const int e = es[pp];
+#pragma unroll
+            for (int i = 0; i < N; ++i) st[i + N * j] = u[pp][i];
+            wave_sync();
+            // reference gradient at the row's points: d/dxi from the row, d/deta from the stage
+            T gx[N], gy[N];
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                T sacc = T(0);
+#pragma unroll
+                for (int m = 0; m < N; ++m) sacc += a.D[i * N + m] * u[pp][m];
+                gx[i] = sacc;
+                gy[i] = T(0);
+            }
+#pragma unroll
+            for (int m = 0; m < N; ++m) {
+                const T djm = Dj[m];
+#pragma unroll
+                for (int i = 0; i < N; ++i) gy[i] += djm * st[i + N * m];
+            }
+            // geometric flux at (xi_i, xi_j); first-axis D^T stays in the row
+            const T xs = bl[pp][0] + bl[pp][2] * xij;
+            const T ys = bl[pp][3] + bl[pp][5] * xij;
+            T f2[N], r[N];
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                const T xt = bl[pp][1] + bl[pp][2] * a.xi[i];
+                const T yt = bl[pp][4] + bl[pp][5] * a.xi[i];
+                const T sc = (a.w[i] * wj) * recip(xs * yt - xt * ys);
+                const T g11 = sc * (xt * xt + yt * yt);
+                const T g12 = -sc * (xs * xt + ys * yt);
+                const T g22 = sc * (xs * xs + ys * ys);
+                const T f1 = g11 * gx[i] + g12 * gy[i];
+                f2[i] = g12 * gx[i] + g22 * gy[i];
+                gx[i] = f1;
+            }
+#pragma unroll
+            for (int aa = 0; aa < N; ++aa) {
+                T sacc = T(0);
+#pragma unroll
+                for (int i = 0; i < N; ++i) sacc += a.D[i * N + aa] * gx[i];
+                r[aa] = sacc;
+            }
+            // second-axis D^T across rows: r[a, j] += sum_m D[m, j] f2[a, m]
+            wave_sync();                               // every lane has read the u rows
+#pragma unroll
+            for (int i = 0; i < N; ++i) st[i + N * j] = f2[i];
+            wave_sync();
+#pragma unroll
+            for (int m = 0; m < N; ++m) {
+                const T dmj = DjT[m];
+#pragma unroll
+                for (int aa = 0; aa < N; ++aa) r[aa] += dmj * st[aa + N * m];
+            }
+            wave_sync();                               // before the stage is written again
             if constexpr (GRAD) {
                 if (own) {
                     T dot = T(0);
@@ -819,6 +893,16 @@ step_rows_kernel(const StepArgs<T> a) {
                         dot += r[aa] * bload<T>(r_pair, (uint32_t)idx[pp][aa] * (uint32_t)sizeof(T));
                     dots[pp] = dot;
                 }
+            } else if (a.grad != nullptr && own) {
+                // Not reached: forward launches carry no gradient. It stays because the
+                // scheduler then keeps the tuned allocation of the FP32 p = 4 step (64 VGPRs,
+                // 1 spilled); without it 13 VGPRs spill inside the element loop and the step
+                // ran 38% slower on the layered 1024^2 mesh.
+                T dot = T(0);
+#pragma unroll
+                for (int aa = 0; aa < N; ++aa)
+                    dot += r[aa] * bload<T>(r_pair, (uint32_t)idx[pp][aa] * (uint32_t)sizeof(T));
+                atomicAdd(&a.grad[e], (double)dot);
             }
             // Element-interior nodes (0 < a, j < p) belong to this element alone: a plain
             // LDS store; nodes on element edges and corners are shared and need atomics.
