@@ -163,12 +163,16 @@ def _copy_counter(d, name):
     return sum(vals) / len(vals)
 
 
-def profile_summary(d, kernel, steps, counter_steps):
+def profile_summary(d, kernel, steps, counter_steps, per_step=1):
     """Markdown summary of rocprofv3 runs under d: trace/ (kernel trace + stats) and, if
     present, fetch/, write/ (FETCH_SIZE, WRITE_SIZE with the copy calibration) and tcc/
-    (TCC_HIT_sum, TCC_MISS_sum). Averages use the last ``steps`` dispatches of ``kernel``
-    in the trace and the last ``counter_steps`` in the counter runs (the timed steps)."""
+    (TCC_HIT_sum, TCC_MISS_sum). Averages use the last ``steps`` steps of ``kernel`` in the
+    trace and the last ``counter_steps`` in the counter runs (the timed steps); a step
+    launches ``kernel`` ``per_step`` times (one launch per colour for the colour scatter),
+    and the figures are per dispatch."""
     out = []
+    steps *= per_step
+    counter_steps *= per_step
     stats = _rows(os.path.join(d, "trace"), "*kernel_stats.csv")
     trace = [r for r in _rows(os.path.join(d, "trace"), "*kernel_trace.csv") if kernel in r["Kernel_Name"]]
     durs = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in trace][-steps:]
@@ -181,7 +185,10 @@ def profile_summary(d, kernel, steps, counter_steps):
     out.append("")
     out.append(f"`{kernel}`: last {len(durs)} dispatches (the timed steps) average {avg_us:.1f} us, "
                f"min {min(durs):.1f}, max {max(durs):.1f}.")
-    rec = {"kernel": kernel, "dispatches": len(durs), "avg_us": avg_us, "sources_sha256": sources_sha256()}
+    if per_step > 1:
+        out.append(f"{per_step} dispatches per step: {avg_us * per_step:.1f} us of `{kernel}` per step.")
+    rec = {"kernel": kernel, "dispatches": len(durs), "avg_us": avg_us, "dispatches_per_step": per_step,
+           "sources_sha256": sources_sha256()}
     if os.path.isdir(os.path.join(d, "fetch")) and os.path.isdir(os.path.join(d, "write")):
         f_kib = _counter(os.path.join(d, "fetch"), "FETCH_SIZE", kernel, counter_steps)
         w_kib = _counter(os.path.join(d, "write"), "WRITE_SIZE", kernel, counter_steps)
@@ -202,6 +209,36 @@ def profile_summary(d, kernel, steps, counter_steps):
         m = _counter(os.path.join(d, "tcc"), "TCC_MISS_sum", kernel, counter_steps)
         out.append(f"L2 (TCC) hit rate {h / (h + m):.3f} ({h:.0f} hits, {m:.0f} misses per dispatch).")
         rec.update({"l2_hit": h / (h + m)})
+    # other counter passes (pmc*/): every counter of the kernel, averaged per dispatch
+    pmc = {}
+    for sub in sorted(glob.glob(os.path.join(d, "pmc*"))):
+        rows = [r for r in _rows(sub, "*counter_collection.csv") if kernel in r["Kernel_Name"]]
+        for name in sorted({r["Counter_Name"] for r in rows}):
+            vals = [float(r["Counter_Value"]) for r in rows if r["Counter_Name"] == name][-counter_steps:]
+            pmc[name] = sum(vals) / len(vals)
+    if pmc:
+        out.append("")
+        out.append("| counter (per dispatch) | value |")
+        out.append("|---|---|")
+        for name, v in pmc.items():
+            out.append(f"| {name} | {v:.4g} |")
+        ratios = {}
+        wc = pmc.get("SQ_WAVE_CYCLES")
+        if wc:
+            for name, label in (("SQ_ACTIVE_INST_VALU", "VALU issue per wave-cycle"),
+                                ("SQ_ACTIVE_INST_LDS", "LDS issue per wave-cycle"),
+                                ("SQ_ACTIVE_INST_VMEM", "VMEM issue per wave-cycle"),
+                                ("SQ_WAIT_INST_ANY", "waiting on s_waitcnt per wave-cycle"),
+                                ("SQ_WAIT_ANY", "waiting (any) per wave-cycle")):
+                if name in pmc:
+                    ratios[label] = pmc[name] / wc
+        if "SQ_LDS_BANK_CONFLICT" in pmc and pmc.get("SQ_ACTIVE_INST_LDS"):
+            ratios["LDS bank-conflict cycles per LDS-active cycle"] = pmc["SQ_LDS_BANK_CONFLICT"] / pmc["SQ_ACTIVE_INST_LDS"]
+        if wc and pmc.get("SQ_BUSY_CYCLES"):
+            ratios["resident waves per busy SQ cycle (all CUs of an SE)"] = wc / pmc["SQ_BUSY_CYCLES"]
+        for k, v in ratios.items():
+            out.append(f"- {k}: {v:.3f}")
+        rec.update({"pmc": pmc, "pmc_ratios": ratios})
     for log_name in ("trace.log", "fetch.log"):
         lp = os.path.join(d, log_name)
         if os.path.exists(lp):
@@ -310,9 +347,11 @@ def main():
     ap.add_argument("--kernel", default="step_rows_kernel", help="kernel of --profile-summary")
     ap.add_argument("--counter-steps", type=int, default=10,
                     help="--steps of the counter runs summarised by --profile-summary")
+    ap.add_argument("--per-step", type=int, default=1,
+                    help="--profile-summary: launches of --kernel per step")
     args = ap.parse_args()
     if args.profile_summary:
-        print(profile_summary(args.profile_summary, args.kernel, args.steps, args.counter_steps))
+        print(profile_summary(args.profile_summary, args.kernel, args.steps, args.counter_steps, args.per_step))
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); multi-GPU sharding is a "

@@ -30,6 +30,7 @@ import numpy as np
 __all__ = [
     "Workload",
     "grid_mesh",
+    "tri_mesh",
     "layered_c",
     "workload",
     "WORKLOADS",
@@ -123,6 +124,23 @@ def grid_mesh(nx: int, ny: int, Lx: float, Ly: float, jitter: float = 0.0,
     xc = 0.5 * (xs[i] + xs[i + 1])
     yc = 0.5 * (ys[j] + ys[j + 1])
     return vxy, quads, xc, yc
+
+
+def tri_mesh(nx: int, ny: int, Lx: float, Ly: float, jitter: float = 0.0, seed: int = SEEDS["mesh"]):
+    """Triangle mesh: the jittered quad lattice of ``grid_mesh`` with every cell cut into two
+    CCW triangles along the diagonal that alternates with (i + j) parity, cell by cell.
+
+    Returns ``(vxy [Nv,2] f64, tris [2E,3] i32, xc, yc)``; (xc, yc) is the unjittered centre
+    of each triangle's cell, used to sample wave-speed models."""
+    vxy, quads, xc, yc = grid_mesh(nx, ny, Lx, Ly, jitter=jitter, seed=seed)
+    i = np.arange(quads.shape[0]) % nx
+    j = np.arange(quads.shape[0]) // nx
+    a = (i + j) % 2 == 0                      # diagonal v0-v2, else v1-v3
+    v0, v1, v2, v3 = quads.T
+    t1 = np.where(a[:, None], np.stack([v0, v1, v2], 1), np.stack([v0, v1, v3], 1))
+    t2 = np.where(a[:, None], np.stack([v0, v2, v3], 1), np.stack([v1, v2, v3], 1))
+    tris = np.stack([t1, t2], axis=1).reshape(-1, 3).astype(np.int32)
+    return vxy, tris, np.repeat(xc, 2), np.repeat(yc, 2)
 
 
 def layered_c(yc: np.ndarray, Ly: float, n_layers: int = 6, c_top: float = 1500.0,
@@ -222,10 +240,22 @@ def workload(name: str, n: Optional[int] = None, nsteps: Optional[int] = None,
                       ckpt_every=40, c2_init=c0 * c0)
         wl.anomaly_xy = anomaly
         return wl
+    if name == "tri2000":
+        # The paper's single-layer benchmark shape (Sec. 5): a 2000 x 1000 domain of near-uniform
+        # unstructured triangles, p=5 (21 local nodes), constant wave speed; 500 x 250 jittered
+        # cells cut into 250k triangles, c = 1500, Ricker 15 Hz at the centre, 128 receivers.
+        nx = n or 500
+        Lx, Ly = 2000.0, 1000.0
+        vxy, tris, xc, yc = tri_mesh(nx, max(1, nx // 2), Lx, Ly, jitter=0.2)
+        c = np.full(tris.shape[0], 1500.0)
+        return Workload(name, p or 5, nx, max(1, nx // 2), Lx, Ly, vxy, tris, c * c,
+                        np.array([[Lx / 2, Ly / 2]]), np.zeros(1, np.int32), 1,
+                        _top_receivers(Lx, Ly), 15.0, nsteps or 1000, precision="f32",
+                        orders=("hilbert", "morton", "lex", "random"))
     raise KeyError(f"unknown workload {name!r}")
 
 
-WORKLOADS = ("homog64", "layered1024", "graded1414", "batch512", "adjoint512")
+WORKLOADS = ("homog64", "layered1024", "graded1414", "batch512", "adjoint512", "tri2000")
 
 
 def random_field(n_nodes: int, n_shots: int = 1, seed: int = 7) -> np.ndarray:
