@@ -41,7 +41,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
-ALL_LEGS = ("main", "fp64", "scatter", "heun", "batch", "adjoint", "orders", "graded", "cpu")
+ALL_LEGS = ("main", "fp64", "scatter", "heun", "tri", "batch", "adjoint", "orders", "graded", "cpu")
 CHUNKS = 5                     # the timed steps are event-timed in this many chunks (median)
 KERNEL_SOURCES = ("kernels.hip", "kernels.h", "api.hip", "plan.cpp", "plan.h")
 HEADLINE_PROFILE = os.path.join(ROOT, "profiles", "step_rows_kernel_layered1024_f32_hilbert.md")
@@ -334,14 +334,15 @@ def main():
                     choices=["hilbert", "morton", "lex", "random", "connectivity", "distance"],
                     help="element order of the headline leg")
     ap.add_argument("--precision", default="f32", choices=["f32", "f64"], help="headline precision")
-    ap.add_argument("--workload", default="layered1024", choices=["layered1024", "graded1414", "batch512"],
+    ap.add_argument("--workload", default="layered1024",
+                    choices=["layered1024", "graded1414", "batch512", "tri2000"],
                     help="headline workload (default: the layered 1024^2 p=4 mesh)")
     ap.add_argument("--formulation", default="leapfrog", choices=["leapfrog", "heun"],
                     help="headline formulation: second-order leapfrog or the first-order system with Heun")
     ap.add_argument("--scatter", default="auto", choices=["auto", "lds_atomic", "colour", "atomic"],
                     help="headline scatter: owner-tile LDS (auto), colour passes or global atomics")
     ap.add_argument("--copy-calib", action="store_true",
-                    help="run only the 1 GiB device copy with the headline (for the counter runs)")
+                    help="headline leg only, as in the counter runs (the 1 GiB copy always runs first)")
     ap.add_argument("--profile-summary", default=None, metavar="DIR",
                     help="summarise rocprofv3 CSV output under DIR (no GPU) and exit")
     ap.add_argument("--kernel", default="step_rows_kernel", help="kernel of --profile-summary")
@@ -357,7 +358,7 @@ def main():
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); multi-GPU sharding is a "
               "design note, not part of this build.", file=sys.stderr)
         sys.exit(2)
-    legs = ("main",) if args.quick else tuple(x for x in args.legs.split(",") if x)
+    legs = ("main",) if (args.quick or args.copy_calib) else tuple(x for x in args.legs.split(",") if x)
 
     cpu = None
     if "cpu" in legs:
@@ -388,8 +389,6 @@ def main():
     copy_gbs = 2 * 4 * (1 << 28) / sec / 1e9
     out["copy_calib"] = {"bytes_per_launch": 2 * 4 * (1 << 28), "GBs": copy_gbs}
     del src, dst
-    if args.copy_calib:
-        legs = ("main",)
     # ---------------------------------------------------------------- headline
     wl = workloads.workload(args.workload, n=args.n)
     label = f"{args.workload} n={wl.nx} p={wl.p} {args.precision} {args.order} S={wl.n_shots}"
@@ -445,6 +444,21 @@ def main():
         out["heun"] = leg_summary(sh, sph, "layered1024 p4 f32 hilbert S=1 first-order Heun")
         out["heun"]["time_ratio_vs_leapfrog"] = sph / (main_leg["us_per_step"] / 1e6)
         sh.close()
+    if "tri" in legs:
+        # the paper's own element: 250k triangles, p = 5 (21 Blyth-Pozrikidis nodes), the
+        # single-layer benchmark shape, in the curve order, the generator order and random
+        log("[bench] tri leg: 250k triangles p=5 (the paper's element), FP32 / FP64")
+        wt = workloads.workload("tri2000")
+        out["tri"] = {}
+        for prec, order in (("f32", "hilbert"), ("f32", "lex"), ("f32", "random"), ("f64", "hilbert")):
+            st_, _ = make_sim(sem, wt, prec, order)
+            spt, _, _ = time_steps(torch, st_, min(args.steps, 200), 10)
+            lg = leg_summary(st_, spt, f"tri2000 p5 {prec} {order}")
+            lg["n_colours"] = st_.info()["n_colours"]
+            out["tri"][f"{prec}_{order}"] = {k: lg[k] for k in (
+                "gdof_steps_per_s", "us_per_step", "alg_bytes_per_step", "achieved_GBs", "hbm_frac",
+                "halo_ratio", "setup_s", "reorder_s", "n_colours", "n_nodes", "n_elements")}
+            st_.close()
     if "graded" in legs:
         log("[bench] graded leg: 1414^2 quads graded 1:8, p=5, FP32, Hilbert / Morton / random")
         wg = workloads.workload("graded1414")

@@ -89,8 +89,22 @@ typedef struct {
     int64_t n_vertices;
     const double* vxy;       /* [n_vertices][2] vertex coordinates                    */
     int64_t n_elements;
-    const int32_t* quad;     /* [n_elements][4] CCW corner vertex ids                  */
+    const int32_t* quad;     /* [n_elements][vertices_per_element] CCW vertex ids      */
     const double* c2;        /* [n_elements] squared wave speed, > 0                   */
+    int32_t vertices_per_element;
+                             /* 4 (or 0): quadrilaterals, GLL tensor nodes of order p.  *
+                              * 3: the paper's element (Sec. 4.2): affine triangles     *
+                              * with the (p+1)(p+2)/2 Blyth-Pozrikidis nodes (GLL nodes *
+                              * on every edge) and the nodal basis dual to them, the    *
+                              * nodes doubling as quadrature points (weights = integrals *
+                              * of the basis functions). Odd p only (the weights are not *
+                              * all positive at even p); leapfrog, LDS scatter; one     *
+                              * launch per shot; default dt = 0.6 times the estimated   *
+                              * stability limit 2 / sqrt(lambda_max). Local node (i, j) *
+                              * at x = (1 + 2 v_i - v_j - v_k) / 3, y likewise, k =     *
+                              * p - i - j, v the GLL nodes on [0, 1]; original numbering *
+                              * as for quadrilaterals (vertices, edge nodes by first    *
+                              * appearance over local edges 0..2, interior nodes).     */
 } sem_mesh;
 
 /* Options of sem_create. Zero-initialise, then set what is needed. */
@@ -158,6 +172,7 @@ typedef struct {
     int32_t n_colours;       /* colours of the greedy element colouring in the element  *
                               * order (Sec. 5; computed for every context)              */
     int32_t scatter;         /* the sem_scatter in use (AUTO resolved)                   */
+    int32_t vertices_per_element; /* 4 quadrilaterals, 3 triangles                   */
     double growth_per_step;  /* largest per-step amplification of the time stepper at    *
                               * h^2 lambda_max: 1 for leapfrog below dt_stable; for Heun *
                               * sqrt(1 + (h^2 lambda_max)^2 / 4), above 1 for any h     *
@@ -229,16 +244,6 @@ int sem_set_field(sem_ctx* ctx, int32_t which, const void* dev);
 /* One application r = K u of the assembled stiffness (Eq. R with the second-order flux),
  * both device buffers [n_shots][n_nodes] in original numbering. For operator checks. */
 int sem_apply_stiffness(sem_ctx* ctx, const void* u_dev, void* r_dev);
-
-/* sem_apply_stiffness without any device allocation, for callers that cannot allocate
- * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
- * The permuted input and the result are staged in a static per-device scratch array of
- * 64 MiB (held by every device the library runs on until the process ends), so
- * n_nodes * n_shots * word size must be <= 32 MiB (else INVALID_ARG, nothing launched).
- * Asynchronous on the context stream (no synchronisation). All calls on one device share the
- * scratch: calls that can overlap in time on one device (other streams, other threads, other
- * contexts on the device) race and must be serialised by the caller. */
-int sem_apply_stiffness_noalloc(sem_ctx* ctx, const void* u_dev, void* r_dev);
 
 /* Gradient of a loss of the receiver traces with respect to c^2 of every element.
  * Runs the forward from rest for nsteps steps storing (u, v) every ckpt_every steps, then

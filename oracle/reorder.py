@@ -13,6 +13,7 @@ and append them.
 
 Readings where the paper is silent or garbled:
   * centroid of a quad = vertex average, evaluated as ((X0 + X1) + (X2 + X3)) * 0.25;
+    of a triangle (the paper's element), ((X0 + X1) + X2) / 3;
   * the "bounding box of width sqrt(n_e)" is a W x H grid of cells with
     W = ceil(sqrt(E)), H = ceil(sqrt(E) / r); a centroid maps to cell
     clamp(floor((c - x_min) * W / w_m), 0, W - 1) (same for y with H / h_m);
@@ -51,7 +52,9 @@ MASK64 = (1 << 64) - 1
 
 # ----------------------------------------------------------------------------- step 1-2
 def centroids(vxy, quads):
-    X = vxy[quads]                                       # [E, 4, 2]
+    X = vxy[quads]                                       # [E, 4, 2] or [E, 3, 2]
+    if X.shape[1] == 3:
+        return ((X[:, 0] + X[:, 1]) + X[:, 2]) / 3.0
     return ((X[:, 0] + X[:, 1]) + (X[:, 2] + X[:, 3])) * 0.25
 
 

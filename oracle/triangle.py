@@ -281,3 +281,26 @@ class TriSEM(_solver.SEM):
         spacing rule of the quadrilaterals does not bound the spectrum of this element: at
         p = 7 the largest stable CFL number on the smallest node distance is about 0.12."""
         return frac * 2.0 / np.sqrt(self.lambda_max())
+
+
+def sampled_rows(vxy, tris, c2, p, conn, nodes, u):
+    """(K u)[nodes] and the lumped mass M[nodes], one node at a time from the element
+    matrices of the triangles around each node (Eqs. R and A-bar restricted to the rows of
+    the sampled nodes); ``u`` is [n_nodes]. For meshes too large to assemble."""
+    _, _, om = reference_operators(p)
+    start, elem, slot = _solver.node_incidence(conn, int(conn.max()) + 1)
+    nodes = np.asarray(nodes, dtype=np.int64)
+    ks = [np.arange(start[v], start[v + 1]) for v in nodes]
+    els = np.unique(np.concatenate([elem[k] for k in ks]))
+    Ke = element_stiffness(vxy, tris, p, c2, elements=els)
+    _, det = jacobians(vxy, np.asarray(tris)[els])
+    pos = {int(e): i for i, e in enumerate(els)}
+    u = np.asarray(u, dtype=np.float64)
+    r = np.zeros(nodes.size)
+    M = np.zeros(nodes.size)
+    for i, k in enumerate(ks):
+        for e, q in zip(elem[k], slot[k]):
+            j = pos[int(e)]
+            r[i] += Ke[j, q] @ u[conn[e]]
+            M[i] += om[q] * det[j]
+    return r, M

@@ -44,6 +44,7 @@ def build(verbose: bool = False) -> str:
         objs = []
         jobs = [
             (os.path.join(CSRC, "plan.cpp"), COMMON + ["-ffp-contract=off"]),
+            (os.path.join(CSRC, "tri.cpp"), COMMON + ["-ffp-contract=off"]),
             (os.path.join(CSRC, "kernels.hip"), COMMON + DEVICE + ["-x", "hip"]),
             (os.path.join(CSRC, "api.hip"), COMMON + DEVICE + ["-x", "hip"]),
         ]

@@ -6,7 +6,6 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
-#include <mutex>
 #include <new>
 #include <numeric>
 #include <random>
@@ -27,12 +26,6 @@ struct DevBuf {
 };
 
 }  // namespace
-
-// Scratch of the allocation-free stiffness apply: the permuted input and the result of one
-// call, each at most half of it. Every device the library runs on holds its own copy for the
-// life of the process; calls on one device share it.
-constexpr size_t kScratchBytes = (size_t)64 << 20;
-static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 struct sem_ctx {
     sem::Plan plan;
@@ -76,6 +69,7 @@ struct sem_ctx {
     // lists with new node ids, the element array position -> new element index, and the
     // launch ranges of the element arrays (one per colour; [0, E) for ATOMIC)
     DevBuf racc, src_node, rec_node;
+    DevBuf tri_S;                     // triangles: reference matrices [3][nq][nq]
     std::vector<int32_t> elem_slot;
     std::vector<int64_t> ranges;
 };
@@ -159,6 +153,7 @@ sem::StepArgs<T> base_args(sem_ctx* c) {
     a.n_rec = c->n_rec;
     a.f0 = c->f0;
     a.t0 = c->t0;
+    a.tri_S = (const T*)c->tri_S.p;
     for (int i = 0; i < P.n * P.n; ++i) a.D[i] = (T)P.D[i];
     for (int i = 0; i < P.n; ++i) {
         a.xi[i] = (T)P.xi[i];
@@ -170,11 +165,13 @@ sem::StepArgs<T> base_args(sem_ctx* c) {
 // accumulator bytes of the largest tile: all owned nodes, or (64-shot kernel, FP64
 // accumulators in either precision) the owned nodes of two or more elements
 size_t lds_bytes(const sem_ctx* c) {
-    if (c->geo >= sem::kGeoShots) return (size_t)c->plan.max_shared * c->SL * sizeof(double);
+    if (c->geo >= sem::kGeoShots && c->geo < sem::kGeoTri)
+        return (size_t)c->plan.max_shared * c->SL * sizeof(double);
     return (size_t)c->plan.max_owned * c->SL * sizeof(double);
 }
 
 bool row_kernel(const sem_ctx* c);
+bool shot_major(const sem_ctx* c);
 
 // One step-kernel launch over all tiles. The row kernel (one shot lane) keeps the state
 // shot-major [S][N] and is launched once per shot with every per-shot array offset.
@@ -214,7 +211,7 @@ template <typename T>
 int launch(sem_ctx* c, const sem::StepArgs<T>& a) {
     if (c->scatter != SEM_SCATTER_LDS_ATOMIC) return global_launch<T>(c, a);
     const int64_t nt = (int64_t)c->plan.tile_eb.size() - 1;
-    if (!row_kernel(c) || c->S == 1) {
+    if (!shot_major(c) || c->S == 1) {
         SEM_HIP(c, sem::launch_step<T>(c->plan.p, c->SL, c->geo, nt, lds_bytes(c), a, c->stream));
         return SEM_OK;
     }
@@ -406,27 +403,6 @@ int power_iteration(sem_ctx* c, int iters) {
     return zero_state<T>(c);
 }
 
-// Device address of the scratch array on the context's device (current), looked up once per
-// device; the array's name is only a host-side stand-in and is never passed to a kernel.
-constexpr int kMaxDevices = 64;
-std::mutex g_scratch_mu;
-void* g_scratch_ptr[kMaxDevices] = {};
-
-int scratch_address(sem_ctx* c, void** out) {
-    if (c->device < 0 || c->device >= kMaxDevices)
-        return fail(c, SEM_ERR_INVALID_ARG, "device ordinal out of range for the scratch table");
-    std::lock_guard<std::mutex> lock(g_scratch_mu);
-    if (!g_scratch_ptr[c->device]) {
-        void* p = nullptr;
-        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
-        if (e != hipSuccess || !p)
-            return fail(c, SEM_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
-        g_scratch_ptr[c->device] = p;
-    }
-    *out = g_scratch_ptr[c->device];
-    return SEM_OK;
-}
-
 int check_ctx(const sem_ctx* c) { return c ? SEM_OK : SEM_ERR_INVALID_ARG; }
 
 int need_device(sem_ctx* c) {
@@ -439,8 +415,11 @@ int set_device(sem_ctx* c) {
     return SEM_OK;
 }
 
-bool shots_kernel(const sem_ctx* c) { return c->geo >= sem::kGeoShots; }
+bool shots_kernel(const sem_ctx* c) { return c->geo >= sem::kGeoShots && c->geo < sem::kGeoTri; }
 bool row_kernel(const sem_ctx* c) { return c->geo > 0 && c->geo < sem::kGeoShots; }
+bool tri_kernel(const sem_ctx* c) { return c->geo >= sem::kGeoTri; }
+// state [S][N] (shot-major, one launch per shot) instead of [N][S]
+bool shot_major(const sem_ctx* c) { return row_kernel(c) || tri_kernel(c); }
 
 // Element arrays in the layout of the context's kernel: the single-shot row kernel reads
 // element-major records (node ids [E][nq]; [E][8] = bilinear coefficients, c^2, 0); the
@@ -453,6 +432,23 @@ int upload_geometry(sem_ctx* c) {
     const int64_t nq = P.nq, ne = P.ne;
     // the kernels address these arrays with 32-bit byte offsets
     const int64_t ni = (int64_t)(P.p - 1) * (P.p - 1);
+    if (tri_kernel(c)) {
+        // conn [E][nq], record [E][4] = g11, g12, g22, c^2 (curve order); reference matrices
+        if ((double)ne * nq * 4.0 >= 4294967296.0 || (double)ne * 4 * sizeof(T) >= 4294967296.0)
+            return fail(c, SEM_ERR_INVALID_ARG, "element arrays exceed 4 GiB (32-bit buffer offsets)");
+        std::vector<int32_t> cb((size_t)ne * nq);
+        std::vector<double> gb((size_t)ne * 4);
+        for (int64_t k = 0; k < ne; ++k) {
+            const int64_t e = c->elem_slot[k];
+            for (int64_t q = 0; q < nq; ++q) cb[k * nq + q] = P.conn_soa[q * ne + e];
+            for (int j = 0; j < 3; ++j) gb[k * 4 + j] = P.tri_G[(size_t)j * ne + e];
+            gb[k * 4 + 3] = P.c2[e];
+        }
+        SEM_HIP(c, upload(c, c->conn, cb));
+        SEM_HIP(c, upload_real(c, c->G, gb));
+        SEM_HIP(c, upload_real(c, c->tri_S, P.tri_S));
+        return SEM_OK;
+    }
     const int64_t words = shots_kernel(c) ? 3 * nq + 1 + ni : row_kernel(c) ? 8 : 3 * nq;
     const int64_t n_rec = shots_kernel(c) || row_kernel(c) ? ne : (ne + 63) / 64 * 64;
     if ((double)n_rec * words * sizeof(T) >= 4294967296.0 || (double)n_rec * nq * 4.0 >= 4294967296.0)
@@ -686,7 +682,7 @@ template <typename T>
 int apply_into(sem_ctx* c, const void* u_dev, void* r_dev, void* tin, void* tout) {
     const int64_t N = c->plan.nn;
     SEM_HIP(c, sem::launch_nodes_from_original<T>((const T*)u_dev, (T*)tin, (const int32_t*)c->n2o_node.p, N,
-                                                  c->S, row_kernel(c), c->stream));
+                                                  c->S, shot_major(c), c->stream));
     sem::StepArgs<T> a = base_args<T>(c);
     a.u_in = (const T*)tin;
     a.mode = 1;
@@ -694,7 +690,7 @@ int apply_into(sem_ctx* c, const void* u_dev, void* r_dev, void* tin, void* tout
     int rc = launch<T>(c, a);
     if (rc) return rc;
     SEM_HIP(c, sem::launch_nodes_to_original<T>((const T*)tout, (T*)r_dev, (const int32_t*)c->n2o_node.p, N,
-                                                c->S, row_kernel(c), c->stream));
+                                                c->S, shot_major(c), c->stream));
     return SEM_OK;
 }
 
@@ -864,7 +860,14 @@ int sem_create(const sem_mesh* mesh, const sem_options* opt, sem_ctx** out) {
     c->precision = opt->precision;
     c->wsize = opt->precision == SEM_F64 ? 8 : 4;
     c->S = opt->n_shots;
-    c->SL = pick_shot_lanes(c->S, opt->shot_lanes);
+    const int nvpe = mesh->vertices_per_element == 0 ? 4 : mesh->vertices_per_element;
+    if (nvpe != 3 && nvpe != 4) {
+        g_create_error = "vertices_per_element must be 0 or 4 (quadrilaterals) or 3 (triangles)";
+        delete c;
+        return SEM_ERR_INVALID_ARG;
+    }
+    // triangles run one shot per launch of the triangle kernel
+    c->SL = nvpe == 3 ? (opt->shot_lanes > 1 ? -1 : 1) : pick_shot_lanes(c->S, opt->shot_lanes);
     if (c->SL < 1 || c->SL > 64 || (c->SL & (c->SL - 1)) || c->S % c->SL) {
         g_create_error = "shot_lanes must be a power of two <= 64 dividing n_shots";
         delete c;
@@ -879,7 +882,13 @@ int sem_create(const sem_mesh* mesh, const sem_options* opt, sem_ctx** out) {
     m.vxy = mesh->vxy;
     m.quad = mesh->quad;
     m.c2 = mesh->c2;
+    m.nvpe = nvpe;
     c->mesh = m;                                  // valid until sem_create returns
+    if (nvpe == 3 && opt->formulation != SEM_FORM_LEAPFROG) {
+        g_create_error = "triangles run the second-order leapfrog formulation";
+        delete c;
+        return SEM_ERR_INVALID_ARG;
+    }
     if (opt->formulation != SEM_FORM_LEAPFROG && opt->formulation != SEM_FORM_HEUN) {
         g_create_error = "unknown formulation";
         delete c;
@@ -899,8 +908,8 @@ int sem_create(const sem_mesh* mesh, const sem_options* opt, sem_ctx** out) {
     // AUTO: owner-tile LDS accumulation, measured fastest for every kernel (colour passes
     // and global atomics both move r through L2 and HBM)
     c->scatter = opt->scatter == SEM_SCATTER_AUTO ? SEM_SCATTER_LDS_ATOMIC : opt->scatter;
-    if (c->scatter != SEM_SCATTER_LDS_ATOMIC && (c->S != 1 || opt->formulation != SEM_FORM_LEAPFROG)) {
-        g_create_error = "the COLOUR and ATOMIC scatters run the single-shot leapfrog step (n_shots = 1)";
+    if (c->scatter != SEM_SCATTER_LDS_ATOMIC && (c->S != 1 || opt->formulation != SEM_FORM_LEAPFROG || nvpe != 4)) {
+        g_create_error = "the COLOUR and ATOMIC scatters run the single-shot leapfrog step on quadrilaterals";
         delete c;
         return SEM_ERR_INVALID_ARG;
     }
@@ -930,6 +939,11 @@ int sem_create(const sem_mesh* mesh, const sem_options* opt, sem_ctx** out) {
     }
     po.tile_items = pick_tile_items(opt->p, c->SL, row_block, opt->tile_items);
     if (opt->tile_items <= 0 && c->SL == 1) po.tile_items = epb;
+    if (nvpe == 3 && opt->tile_items <= 0) {
+        // triangles: several passes of 64 / nq elements per wave, about 96 elements a tile
+        const int epb_tri = (64 / sem::tri_nq(opt->p)) * (row_block / 64);
+        po.tile_items = std::max(1, (96 + epb_tri - 1) / epb_tri) * epb_tri;
+    }
     // 64 shots: tiles are bounded by the LDS accumulator, not by an element count
     if (opt->tile_items <= 0 && c->SL == 64) po.tile_items = 1 << 20;
     int np = 1;
@@ -943,7 +957,8 @@ int sem_create(const sem_mesh* mesh, const sem_options* opt, sem_ctx** out) {
     }
     // one shot lane: row kernel with in-kernel geometry (shot-major state, a block per tile
     // and shot); 64 shot lanes: one wave per element
-    if (c->SL == 1) c->geo = row_block * 8 + np;
+    if (nvpe == 3) c->geo = sem::kGeoTri + row_block;
+    else if (c->SL == 1) c->geo = row_block * 8 + np;
     // 64 shots: FP32 512 threads, FP64 256 (p = 4: about 100 VGPRs in FP32, 170 in FP64)
     else if (c->SL == 64)
         c->geo = sem::kGeoShots +
@@ -986,6 +1001,8 @@ int sem_create(const sem_mesh* mesh, const sem_options* opt, sem_ctx** out) {
         size_t need = lds_bytes(c);
         if (c->formulation == SEM_FORM_HEUN)
             need = sem::heun_lds_bytes(opt->p, 2, lds_own, c->wsize);
+        else if (tri_kernel(c))
+            need = sem::tri_lds_bytes(opt->p, row_block, lds_own, c->wsize);
         else if (row_kernel(c))
             need = sem::rows_lds_bytes(opt->p, row_block, lds_own, c->wsize);
         if (need > sem::kMaxLds) {
@@ -1003,13 +1020,18 @@ int sem_create(const sem_mesh* mesh, const sem_options* opt, sem_ctx** out) {
     }
     if (!c->host_only) {
         int rc = set_device(c);
-        void* scratch_ptr = nullptr;
-        if (rc == SEM_OK) rc = scratch_address(c, &scratch_ptr);
         if (rc == SEM_OK) rc = c->precision == SEM_F64 ? upload_mesh<double>(c) : upload_mesh<float>(c);
         if (rc == SEM_OK && c->formulation == SEM_FORM_HEUN)
             rc = c->precision == SEM_F64 ? setup_heun<double>(c) : setup_heun<float>(c);
         if (rc == SEM_OK) rc = c->precision == SEM_F64 ? power_iteration<double>(c, 60)
                                                        : power_iteration<float>(c, 60);
+        if (rc == SEM_OK && c->plan.dt_from_stability) {
+            // triangles: the node-spacing rule does not bound the spectrum of the element, so
+            // the default dt is 0.6 of the estimated leapfrog limit
+            c->plan.dt = 0.6 * c->dt_stable;
+            rc = upload_real(c, c->dtminv, c->plan.minv, c->plan.dt) == hipSuccess ? SEM_OK : SEM_ERR_HIP;
+            if (rc) c->err = "upload of dt / M failed";
+        }
         if (rc == SEM_OK && !(c->plan.dt < c->dt_stable)) {
             rc = SEM_ERR_UNSTABLE_DT;
             c->err = "dt = " + std::to_string(c->plan.dt) + " exceeds the stability limit " +
@@ -1041,7 +1063,11 @@ int sem_get_info(const sem_ctx* c, sem_info* info) {
     info->max_owned_nodes = P.max_owned;
     info->tile_items = P.tile_items;
     info->geometry_on_the_fly = row_kernel(c) ? 1 : 0;
-    info->block_threads = shots_kernel(c) ? c->geo - sem::kGeoShots : row_kernel(c) ? c->geo / 8 : sem::kBlock;
+    info->block_threads = tri_kernel(c)     ? c->geo - sem::kGeoTri
+                          : shots_kernel(c) ? c->geo - sem::kGeoShots
+                          : row_kernel(c)   ? c->geo / 8
+                                            : sem::kBlock;
+    info->vertices_per_element = P.nvpe;
     info->n_tiles = P.tile_eb.empty() ? 0 : (int64_t)P.tile_eb.size() - 1;
     info->halo_elements = (int64_t)P.halo.size();
     info->step = c->step;
@@ -1065,6 +1091,13 @@ int sem_get_info(const sem_ctx* c, sem_info* info) {
     const double n = (double)P.n;
     info->alg_flops_per_step = (double)P.ne * c->S * (8.0 * n * n * n + 7.0 * n * n) +
                                (double)P.nn * c->S * 4.0;
+    if (tri_kernel(c)) {
+        // affine triangles: per element nq ids, 3 geometric factors and c^2; per node as above;
+        // three reference-matrix rows per local node: 6 nq^2 flops and the combination
+        info->alg_bytes_per_step = (double)P.ne * (nq * 4.0 + 4.0 * w) + per_node;
+        info->kernel_bytes_per_step = info->alg_bytes_per_step;
+        info->alg_flops_per_step = (double)P.ne * c->S * (6.0 * nq * nq + 6.0 * nq) + (double)P.nn * c->S * 4.0;
+    }
     if (c->formulation == SEM_FORM_HEUN) {
         // one launch per step (the corrector fused with the next predictor); per element:
         // ids and the 8-word record, V^n read and V^{n+1} written (2 nq words each); per
@@ -1212,11 +1245,11 @@ int sem_get_field(sem_ctx* c, int32_t which, void* dev) {
     const void* src = which == SEM_FIELD_U ? c->u[c->cur].p : c->v.p;
     if (c->precision == SEM_F64)
         SEM_HIP(c, sem::launch_nodes_to_original<double>((const double*)src, (double*)dev,
-                                                         (const int32_t*)c->n2o_node.p, c->plan.nn, c->S, row_kernel(c),
+                                                         (const int32_t*)c->n2o_node.p, c->plan.nn, c->S, shot_major(c),
                                                          c->stream));
     else
         SEM_HIP(c, sem::launch_nodes_to_original<float>((const float*)src, (float*)dev,
-                                                        (const int32_t*)c->n2o_node.p, c->plan.nn, c->S, row_kernel(c),
+                                                        (const int32_t*)c->n2o_node.p, c->plan.nn, c->S, shot_major(c),
                                                          c->stream));
     return SEM_OK;
 }
@@ -1233,11 +1266,11 @@ int sem_set_field(sem_ctx* c, int32_t which, const void* dev) {
     c->heun_pred_valid = false;
     if (c->precision == SEM_F64)
         SEM_HIP(c, sem::launch_nodes_from_original<double>((const double*)dev, (double*)dst,
-                                                           (const int32_t*)c->n2o_node.p, c->plan.nn, c->S, row_kernel(c),
+                                                           (const int32_t*)c->n2o_node.p, c->plan.nn, c->S, shot_major(c),
                                                          c->stream));
     else
         SEM_HIP(c, sem::launch_nodes_from_original<float>((const float*)dev, (float*)dst,
-                                                          (const int32_t*)c->n2o_node.p, c->plan.nn, c->S, row_kernel(c),
+                                                          (const int32_t*)c->n2o_node.p, c->plan.nn, c->S, shot_major(c),
                                                          c->stream));
     return SEM_OK;
 }
@@ -1249,27 +1282,6 @@ int sem_apply_stiffness(sem_ctx* c, const void* u_dev, void* r_dev) {
     rc = set_device(c);
     if (rc) return rc;
     return c->precision == SEM_F64 ? apply_t<double>(c, u_dev, r_dev) : apply_t<float>(c, u_dev, r_dev);
-}
-
-int sem_apply_stiffness_noalloc(sem_ctx* c, const void* u_dev, void* r_dev) {
-    if (!c || !u_dev || !r_dev) return SEM_ERR_INVALID_ARG;
-    int rc = need_device(c);
-    if (rc) return rc;
-    rc = set_device(c);
-    if (rc) return rc;
-    const size_t bytes = (size_t)c->plan.nn * c->S * c->wsize;
-    const size_t half = (bytes + 255) & ~(size_t)255;
-    if (2 * half > kScratchBytes)
-        return fail(c, SEM_ERR_INVALID_ARG,
-                    "n_nodes * n_shots * word size = " + std::to_string(bytes) + " bytes exceeds the " +
-                        std::to_string(kScratchBytes / 2) + " bytes of one half of the scratch");
-    void* base = nullptr;
-    rc = scratch_address(c, &base);
-    if (rc) return rc;
-    void* tin = base;
-    void* tout = (unsigned char*)base + half;
-    return c->precision == SEM_F64 ? apply_into<double>(c, u_dev, r_dev, tin, tout)
-                                   : apply_into<float>(c, u_dev, r_dev, tin, tout);
 }
 
 int sem_adjoint_gradient(sem_ctx* c, const void* dL, int64_t nsteps, int32_t ckpt_every, double* grad) {
@@ -1408,7 +1420,7 @@ void sem_destroy(sem_ctx* c) {
                           &c->halo, &c->n2o_node, &c->n2o_elem, &c->u[0], &c->u[1], &c->v,
                           &c->src_b, &c->src_loc, &c->src_shot, &c->src_w, &c->rec_b, &c->rec_loc,
                           &c->rec_idx, &c->u_next, &c->hv[0], &c->hv[1], &c->minv_w, &c->u_pred,
-                          &c->racc, &c->src_node, &c->rec_node};
+                          &c->racc, &c->src_node, &c->rec_node, &c->tri_S};
         for (DevBuf* b : bufs) dev_free(*b);
     }
     delete c;

@@ -10,6 +10,7 @@ namespace sem {
 constexpr int kBlock = 256;     // threads per workgroup of the shot-batch and utility kernels
 constexpr int kRowBlock = 1024; // largest workgroup of the single-shot row kernel
 constexpr int kGeoShots = 1 << 16; // `geo` of the 64-shot kernel: kGeoShots + threads
+constexpr int kGeoTri = 1 << 17;   // `geo` of the triangle kernel: kGeoTri + threads
 constexpr int kMaxP = 7;
 
 // Arguments of the fused step kernel. All arrays use the new (curve) numbering.
@@ -72,6 +73,8 @@ struct StepArgs {
     const int32_t* src_node;
     const int32_t* rec_node;
     int32_t n_src_pts, n_rec_pts;
+    // triangles: reference matrices [3][nq][nq] (Sxx, Sxy + Syx, Syy) of the nodal basis
+    const T* tri_S;
     // 1D GLL nodes, weights and derivative matrix D[i*(p+1) + j] = l_j'(xi_i)
     T xi[kMaxP + 1];
     T w[kMaxP + 1];
@@ -95,6 +98,8 @@ hipError_t launch_node_update(const StepArgs<T>& a, int64_t n, hipStream_t strea
 template <typename T>
 hipError_t launch_global_points(const StepArgs<T>& a, int phase, hipStream_t stream);
 
+// geo = kGeoTri + threads (256/512/1024): the triangle kernel (p odd; conn [E][nq], records
+// [E][4] = det J J^-1 J^-T (11, 12, 22), c^2; reference matrices in tri_S), one shot per launch.
 // geo = threads * 8 + passes (threads 256/512/1024, passes 1/2/4 batched per round of
 // loads): single-shot row kernel, geometric factors computed in-kernel (shot_lanes 1);
 // geo = kGeoShots + threads (256/512/1024): 64-shot kernel, one wave per element
@@ -166,6 +171,12 @@ template <typename T>
 hipError_t launch_heun_stage(int p, int mode, int64_t n_tiles, size_t lds_bytes,
                              const HeunArgs<T>& a, hipStream_t stream);
 
+// Dynamic LDS of one workgroup of the triangle kernel: the per-element stage of nq words
+// (16-byte aligned), the FP64 accumulator and the three prefetch arrays.
+inline size_t tri_lds_bytes(int p, int threads, int64_t lds_own, size_t word) {
+    const int nq = (p + 1) * (p + 2) / 2, nqp = (nq + 3) & ~3, epb = (64 / nq) * (threads / 64);
+    return (size_t)epb * nqp * word + (size_t)lds_own * 8 + (size_t)3 * lds_own * word;
+}
 // Dynamic LDS of one workgroup of the single-shot row kernel: the per-element stage
 // (16-byte aligned rows of nq words), the FP64 accumulator and the three prefetch arrays
 // (v, u, dt/M) of lds_own entries each.

@@ -28,6 +28,10 @@
 #ifndef SEM_MIN_WAVES_F64
 #define SEM_MIN_WAVES_F64 1
 #endif
+// passes of the triangle kernel whose loads are issued together
+#ifndef TRI_NP
+#define TRI_NP 2
+#endif
 
 namespace sem {
 namespace {
@@ -1081,6 +1085,213 @@ hipError_t launch_elems_t(int threads, bool atomic, const StepArgs<T>& a, hipStr
     }
 }
 
+// ---------------------------------------------------------------------------------------
+// The paper's own element (Sec. 4.2): affine triangles with nq = (p+1)(p+2)/2 local nodes on
+// the Blyth-Pozrikidis grid, single shot, owner-tile LDS accumulation with halo
+// recomputation as in step_rows_kernel. nq consecutive lanes of a wave hold the nodes of one
+// element (64 / nq elements per wave). Lane q gathers u at its node into the element's LDS
+// stage and forms r_q = c^2 sum_m (g11 Sxx + g12 Sxy + g22 Syy)[q][m] (u_m - u_q), row q of the three
+// reference matrices held in registers for the whole launch; the stage values are
+// wave-uniform broadcasts. The element record is (g11, g12, g22, c^2), G = det J J^-1 J^-T
+// constant over the element.
+template <typename T, int P, int RB, int NP, bool GRAD>
+__global__ void __attribute__((amdgpu_flat_work_group_size(RB, RB))) tri_rows_kernel(const StepArgs<T> a) {
+    constexpr int NQ = (P + 1) * (P + 2) / 2;
+    constexpr int NQP = (NQ + 3) & ~3;
+    constexpr int EPW = 64 / NQ;
+    constexpr int EPB = EPW * (RB / 64);
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* stage = reinterpret_cast<T*>(smem_raw);          // [EPB][NQP]
+    double* acc = reinterpret_cast<double*>(stage + EPB * NQP);
+    T* pre_v = reinterpret_cast<T*>(acc + a.lds_own);
+    T* pre_u = pre_v + a.lds_own;
+    T* pre_m = pre_u + a.lds_own;
+
+    const int tile = xcd_logical_block();
+    const int nb = a.tile_nb[tile];
+    const int nown = a.tile_nb[tile + 1] - nb;
+    const int eb = a.tile_eb[tile];
+    const int n_own_el = a.tile_eb[tile + 1] - eb;
+    const int hb = a.halo_b[tile];
+    const int n_items = n_own_el + (a.halo_b[tile + 1] - hb);
+    const rsrc_t r_conn = make_rsrc(a.conn, a.conn_bytes);
+    const rsrc_t r_G = make_rsrc(a.G, a.G_bytes);
+    const rsrc_t r_u = make_rsrc(a.u_in, a.state_bytes);
+    const rsrc_t r_pair = make_rsrc(a.u_pair, a.u_pair ? a.state_bytes : 0u);
+    if (a.mode == 0) {
+        const int ndw = nown * (int)(sizeof(T) / 4);
+        const uint32_t off = (uint32_t)nb * (uint32_t)sizeof(T);
+        lds_prefetch<RB>(make_rsrc(a.v, a.state_bytes), off, pre_v, ndw);
+        lds_prefetch<RB>(r_u, off, pre_u, ndw);
+        lds_prefetch<RB>(make_rsrc(a.dtminv, a.state_bytes), off, pre_m, ndw);
+    }
+    for (int i = threadIdx.x; i < nown; i += RB) acc[i] = 0.0;
+    __syncthreads();
+
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int kw = lane / NQ, q = lane - kw * NQ;
+    const int slot = wave * EPW + kw;
+    T* st = stage + slot * NQP;
+    // local node (i, j) of lane q (j outer, i inner); element-interior nodes have i, j, k >= 1
+    int qi = q, qj = 0;
+    while (qj <= P && qi >= P + 1 - qj) { qi -= P + 1 - qj; ++qj; }
+    const bool interior = qi >= 1 && qj >= 1 && P - qi - qj >= 1;
+    T s1[NQ], s2[NQ], s3[NQ];
+    const int qrow = kw < EPW ? q : 0;
+#pragma unroll
+    for (int m = 0; m < NQ; ++m) {
+        s1[m] = a.tri_S[qrow * NQ + m];
+        s2[m] = a.tri_S[(NQ + qrow) * NQ + m];
+        s3[m] = a.tri_S[(2 * NQ + qrow) * NQ + m];
+    }
+    // NP passes at a time: every pass's node ids and records are requested first, then every
+    // pass's gathers, so NP passes cost about one memory round trip
+    for (int base = 0; base < n_items; base += NP * EPB) {
+        int es[NP], node[NP];
+        bool act[NP];
+        T rec[NP][4], uq[NP];
+#pragma unroll
+        for (int pp = 0; pp < NP; ++pp) {
+            const int k = base + pp * EPB + slot;
+            act[pp] = kw < EPW && k < n_items;
+            es[pp] = 0;
+            node[pp] = 0;
+            if (act[pp]) {
+                es[pp] = k < n_own_el ? eb + k : a.halo[hb + k - n_own_el];
+                node[pp] = bload<int>(r_conn, (uint32_t)(es[pp] * NQ + q) * 4u);
+                if constexpr (sizeof(T) == 4) {
+                    const auto v = __builtin_amdgcn_raw_buffer_load_b128(r_G, (uint32_t)es[pp] * 16u, 0, 0);
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) rec[pp][c] = __uint_as_float(v[c]);
+                } else {
+#pragma unroll
+                    for (int c = 0; c < 4; c += 2) {
+                        const auto v = __builtin_amdgcn_raw_buffer_load_b128(r_G, (uint32_t)es[pp] * 32u + 8u * c, 0, 0);
+                        rec[pp][c] = __builtin_bit_cast(double, ((unsigned long long)v[1] << 32) | v[0]);
+                        rec[pp][c + 1] = __builtin_bit_cast(double, ((unsigned long long)v[3] << 32) | v[2]);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int pp = 0; pp < NP; ++pp)
+            uq[pp] = act[pp] ? bload<T>(r_u, (uint32_t)node[pp] * (uint32_t)sizeof(T)) : T(0);
+#pragma unroll
+        for (int pp = 0; pp < NP; ++pp) {
+            const int k = base + pp * EPB + slot;
+            T dot = T(0);
+            if (act[pp]) {
+                const T u = uq[pp];
+                wave_sync();                           // earlier reads of the stage are done
+                st[q] = u;
+                wave_sync();
+                // Every row of the reference matrices sums to zero (K_e 1 = 0), so the row
+                // applies to u_m - u_q: the common part of the element's values cancels before
+                // rounding and the rounded matrices keep the exact null space (in FP32 the plain
+                // product drifts by the rounding of the row sums, which acts on the mean field
+                // every step)
+                T y1 = T(0), y2 = T(0), y3 = T(0);
+#pragma unroll
+                for (int m = 0; m < NQ; ++m) {
+                    const T um = st[m] - u;
+                    y1 += s1[m] * um;
+                    y2 += s2[m] * um;
+                    y3 += s3[m] * um;
+                }
+                const T r = rec[pp][0] * y1 + rec[pp][1] * y2 + rec[pp][2] * y3;    // (Khat_e u_e)_q
+                if constexpr (GRAD) {
+                    if (k < n_own_el) dot = r * bload<T>(r_pair, (uint32_t)node[pp] * (uint32_t)sizeof(T));
+                }
+                const int loc = node[pp] - nb;
+                if ((unsigned)loc < (unsigned)nown) {
+                    if (interior) acc[loc] = (double)(rec[pp][3] * r);
+                    else atomicAdd(&acc[loc], (double)(rec[pp][3] * r));
+                }
+            }
+            if constexpr (GRAD) {
+                // every lane takes part: sum the element's nq lanes, one atomic per own element
+                T tot = T(0);
+                const int lead = (kw < EPW ? kw : 0) * NQ;
+#pragma unroll
+                for (int m = 0; m < NQ; ++m) tot += __shfl(dot, lead + m, 64);
+                if (q == 0 && act[pp] && k < n_own_el) atomicAdd(&a.grad[es[pp]], (double)tot);
+            }
+        }
+    }
+    __builtin_amdgcn_s_waitcnt(0);                     // this wave's LDS prefetches landed
+    __syncthreads();
+
+    if (a.src_b != nullptr) {
+        const int sb = a.src_b[tile], se = a.src_b[tile + 1];
+        if (se > sb) {
+            const T amp = (T)ricker(a.src_t, a.f0, a.t0);
+            for (int i = sb + threadIdx.x; i < se; i += RB)
+                if (a.src_shot[i] == a.shot) atomicAdd(&acc[a.src_loc[i]], -(double)(a.src_w[i] * amp));
+            __syncthreads();
+        }
+    }
+    if (a.inj != nullptr) {
+        const int rb = a.rec_b[tile], re = a.rec_b[tile + 1];
+        if (re > rb) {
+            for (int i = rb + threadIdx.x; i < re; i += RB) {
+                const T val = a.inj[(int64_t)a.rec_idx[i] * a.inj_cols + a.inj_col];
+                atomicAdd(&acc[a.rec_loc[i]], -(double)(val * a.inj_scale));
+            }
+            __syncthreads();
+        }
+    }
+    if (a.mode == 0) {
+        for (int i = threadIdx.x; i < nown; i += RB) {
+            const T vn = pre_v[i] - pre_m[i] * (T)acc[i];
+            const T un = pre_u[i] + a.dt * vn;
+            a.v[nb + i] = vn;
+            a.u_out[nb + i] = un;
+            acc[i] = (double)un;
+        }
+        if (a.trace != nullptr) {
+            const int rb = a.rec_b[tile], re = a.rec_b[tile + 1];
+            if (re > rb) {
+                __syncthreads();
+                for (int i = rb + threadIdx.x; i < re; i += RB)
+                    a.trace[(int64_t)a.rec_idx[i] * a.trace_cols + a.trace_col] = (T)acc[a.rec_loc[i]];
+            }
+        }
+    } else {
+        for (int i = threadIdx.x; i < nown; i += RB)
+            a.r_out[nb + i] = a.mode == 2 ? a.dtminv[nb + i] * (T)acc[i] : (T)acc[i];
+    }
+}
+
+template <typename T, int P, int RB>
+hipError_t launch_tri(int64_t n_tiles, const StepArgs<T>& a, hipStream_t st) {
+    // FP32: TRI_NP passes (about 100 VGPRs, four waves per SIMD either way); FP64: one pass
+    // (two would drop to two waves per SIMD)
+    constexpr int NP = sizeof(T) == 4 ? TRI_NP : 1;
+    auto fn = a.grad != nullptr ? tri_rows_kernel<T, P, RB, NP, true> : tri_rows_kernel<T, P, RB, NP, false>;
+    const size_t lds = tri_lds_bytes(P, RB, a.lds_own, sizeof(T));
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(fn, dim3((unsigned)n_tiles), dim3(RB), lds, st, a);
+    return hipGetLastError();
+}
+
+template <typename T, int P>
+hipError_t launch_tri_t(int threads, int64_t n_tiles, const StepArgs<T>& a, hipStream_t st) {
+    if constexpr (P % 2 == 0) {
+        return hipErrorInvalidValue;                  // triangles run odd p only
+    } else {
+        switch (threads) {
+            case 256: return launch_tri<T, P, 256>(n_tiles, a, st);
+            case 512: return launch_tri<T, P, 512>(n_tiles, a, st);
+            case 1024: return launch_tri<T, P, 1024>(n_tiles, a, st);
+            default: return hipErrorInvalidValue;
+        }
+    }
+}
+
 template <typename T, int P, int SL>
 hipError_t launch_one(int64_t n_tiles, size_t lds, const StepArgs<T>& a, hipStream_t st) {
     auto fn = step_kernel<T, P, SL>;
@@ -1121,6 +1332,10 @@ hipError_t launch_shots(int64_t n_tiles, size_t lds, const StepArgs<T>& a, hipSt
 
 template <typename T, int P>
 hipError_t launch_p(int sl, int geo, int64_t nt, size_t lds, const StepArgs<T>& a, hipStream_t st) {
+    if (geo >= kGeoTri) {
+        if (sl != 1) return hipErrorInvalidValue;
+        return launch_tri_t<T, P>(geo - kGeoTri, nt, a, st);
+    }
     if (geo >= kGeoShots) {
         if (sl != 64) return hipErrorInvalidValue;
         switch (geo - kGeoShots) {

@@ -298,22 +298,23 @@ int32_t nearest_node(const Plan& plan, double px, double py) {
 // neighbours) or, with by_distance, the squared distance to (min x, min y).
 static std::vector<int32_t> vertex_walk(const MeshIn& m, bool by_distance) {
     const int64_t nv = m.nv, ne = m.ne;
-    // elements of every vertex, ascending (corners of a valid quad are distinct)
-    std::vector<int32_t> v2e_b(nv + 1, 0), v2e((size_t)ne * 4);
-    for (int64_t i = 0; i < ne * 4; ++i) v2e_b[m.quad[i] + 1]++;
+    const int K = m.nvpe;
+    // elements of every vertex, ascending (corners of a valid element are distinct)
+    std::vector<int32_t> v2e_b(nv + 1, 0), v2e((size_t)ne * K);
+    for (int64_t i = 0; i < ne * K; ++i) v2e_b[m.quad[i] + 1]++;
     for (int64_t v = 0; v < nv; ++v) v2e_b[v + 1] += v2e_b[v];
     {
         std::vector<int32_t> fill(v2e_b.begin(), v2e_b.end() - 1);
         for (int64_t e = 0; e < ne; ++e)
-            for (int k = 0; k < 4; ++k) v2e[fill[m.quad[4 * e + k]]++] = (int32_t)e;
+            for (int k = 0; k < K; ++k) v2e[fill[m.quad[K * e + k]]++] = (int32_t)e;
     }
     std::vector<int32_t> stamp(nv, -1), nbr;
     auto neighbours = [&](int32_t v) {
         nbr.clear();
         stamp[v] = v;
         for (int32_t i = v2e_b[v]; i < v2e_b[v + 1]; ++i)
-            for (int k = 0; k < 4; ++k) {
-                const int32_t w = m.quad[4 * (int64_t)v2e[i] + k];
+            for (int k = 0; k < K; ++k) {
+                const int32_t w = m.quad[K * (int64_t)v2e[i] + k];
                 if (stamp[w] != v) { stamp[w] = v; nbr.push_back(w); }
             }
     };
@@ -487,7 +488,10 @@ void element_geometry(const Plan& P, const MeshIn& m, int64_t e, double* g11, do
 std::string build_plan(const MeshIn& m, const PlanOptions& opt, Plan& P, int& code) {
     code = SEM_ERR_INVALID_ARG;
     if (opt.p < 1 || opt.p > 7) return "p must be in 1..7";
-    if (m.ne < 1 || m.nv < 4 || !m.vxy || !m.quad || !m.c2) return "empty or null mesh";
+    if (m.nvpe != 3 && m.nvpe != 4) return "elements must have 3 or 4 vertices";
+    if (m.ne < 1 || m.nv < m.nvpe || !m.vxy || !m.quad || !m.c2) return "empty or null mesh";
+    if (m.nvpe == 3 && opt.p % 2 == 0)
+        return "triangles use odd p (the nodal quadrature weights are not all positive at even p)";
     if (opt.elem_order < 0 || opt.elem_order > 5) return "unknown element order";
     if (opt.node_order < 0 || opt.node_order > 1) return "unknown node order";
     if (opt.tile_elems < 0 || (opt.tile_elems == 0 && opt.tile_items < 1)) return "bad tile size";
@@ -498,13 +502,14 @@ std::string build_plan(const MeshIn& m, const PlanOptions& opt, Plan& P, int& co
     P = Plan();
     P.p = opt.p;
     P.n = opt.p + 1;
-    P.nq = P.n * P.n;
+    P.nvpe = m.nvpe;
+    P.nq = m.nvpe == 3 ? tri_nq(opt.p) : P.n * P.n;
     P.ne = m.ne;
     P.nv = m.nv;
     gll_basis(P.p, P.xi, P.w, P.D);
 
     code = SEM_ERR_BAD_MESH;
-    std::string err = number_nodes(m, P.p, P.conn0, P.nn);
+    std::string err = m.nvpe == 3 ? tri_number_nodes(m, P.p, P.conn0, P.nn) : number_nodes(m, P.p, P.conn0, P.nn);
     if (!err.empty()) return err;
     const int n = P.n, nq = P.nq;
     const int64_t ne = P.ne, nn = P.nn;
@@ -514,7 +519,47 @@ std::string build_plan(const MeshIn& m, const PlanOptions& opt, Plan& P, int& co
     P.node_xy.assign(2 * nn, 0.0);
     std::vector<uint8_t> placed(nn, 0);
     double dt_cfl = INFINITY;
-    {
+    if (m.nvpe == 3) {
+        // affine triangles: one Jacobian per element; nodes at the mapped reference nodes;
+        // dt_cfl from the smallest distance between two local nodes (a provisional dt, see
+        // dt_from_stability)
+        G0.assign((size_t)3 * ne, 0.0);
+        err = tri_reference(P.p, P.xi, P.tri_xy, P.tri_w, P.tri_S);
+        if (!err.empty()) return err;
+        std::vector<double> px(nq), py(nq);
+        for (int64_t e = 0; e < ne; ++e) {
+            const int32_t* t = m.quad + 3 * e;
+            const double x0 = m.vxy[2 * t[0]], y0 = m.vxy[2 * t[0] + 1];
+            const double a = m.vxy[2 * t[1]] - x0, c = m.vxy[2 * t[1] + 1] - y0;   // column X1 - X0
+            const double b = m.vxy[2 * t[2]] - x0, d = m.vxy[2 * t[2] + 1] - y0;   // column X2 - X0
+            const double det = a * d - b * c;
+            if (!(det > 0.0)) return "non-positive Jacobian (clockwise or degenerate triangle) in element " +
+                                     std::to_string(e);
+            // det J^-1 J^-T = (1 / det) [[b^2 + d^2, -(a b + c d)], [., a^2 + c^2]]
+            G0[0 * (size_t)ne + e] = (b * b + d * d) / det;
+            G0[1 * (size_t)ne + e] = -(a * b + c * d) / det;
+            G0[2 * (size_t)ne + e] = (a * a + c * c) / det;
+            for (int q = 0; q < nq; ++q) {
+                px[q] = x0 + P.tri_xy[2 * q] * a + P.tri_xy[2 * q + 1] * b;
+                py[q] = y0 + P.tri_xy[2 * q] * c + P.tri_xy[2 * q + 1] * d;
+                const int32_t v = P.conn0[e * nq + q];
+                mass[v] += det * P.tri_w[q];
+                if (!placed[v]) {
+                    placed[v] = 1;
+                    P.node_xy[2 * v] = px[q];
+                    P.node_xy[2 * v + 1] = py[q];
+                }
+            }
+            double dmin = INFINITY;
+            for (int q = 0; q < nq; ++q)
+                for (int r = q + 1; r < nq; ++r) {
+                    const double dx = px[r] - px[q], dy = py[r] - py[q];
+                    dmin = std::min(dmin, std::sqrt(dx * dx + dy * dy));
+                }
+            dt_cfl = std::min(dt_cfl, dmin / std::sqrt(m.c2[e]));
+        }
+        P.dt_from_stability = !(opt.dt > 0.0);
+    } else {
         std::vector<double> g11(nq), g12(nq), g22(nq), det(nq), px(nq), py(nq);
         for (int64_t e = 0; e < ne; ++e) {
             element_geometry(P, m, e, g11.data(), g12.data(), g22.data(), det.data());
@@ -580,9 +625,16 @@ std::string build_plan(const MeshIn& m, const PlanOptions& opt, Plan& P, int& co
         const int64_t H = std::max<int64_t>(1, (int64_t)std::ceil(s / r));
         const double sx = (double)W / wm, sy = (double)H / hm;
         for (int64_t e = 0; e < ne; ++e) {
-            const Corners c = corners(m, e);
-            const double cxm = ((c.x[0] + c.x[1]) + (c.x[2] + c.x[3])) * 0.25;
-            const double cym = ((c.y[0] + c.y[1]) + (c.y[2] + c.y[3])) * 0.25;
+            double cxm, cym;
+            if (m.nvpe == 3) {
+                const int32_t* t = m.quad + 3 * e;
+                cxm = ((m.vxy[2 * t[0]] + m.vxy[2 * t[1]]) + m.vxy[2 * t[2]]) / 3.0;
+                cym = ((m.vxy[2 * t[0] + 1] + m.vxy[2 * t[1] + 1]) + m.vxy[2 * t[2] + 1]) / 3.0;
+            } else {
+                const Corners c = corners(m, e);
+                cxm = ((c.x[0] + c.x[1]) + (c.x[2] + c.x[3])) * 0.25;
+                cym = ((c.y[0] + c.y[1]) + (c.y[2] + c.y[3])) * 0.25;
+            }
             int64_t cx = (int64_t)std::floor((cxm - xmin) * sx);
             int64_t cy = (int64_t)std::floor((cym - ymin) * sy);
             cx = std::min<int64_t>(std::max<int64_t>(cx, 0), W - 1);
@@ -650,8 +702,18 @@ std::string build_plan(const MeshIn& m, const PlanOptions& opt, Plan& P, int& co
 
     // ---------------------------------------------------------------- new-order arrays
     P.conn_soa.resize((size_t)nq * ne);
-    P.G_soa.resize((size_t)3 * nq * ne);
     P.c2.resize(ne);
+    if (m.nvpe == 3) {
+        P.tri_G.resize((size_t)3 * ne);
+        for (int64_t k = 0; k < ne; ++k) {
+            const int64_t e = P.elem_new2old[k];
+            P.c2[k] = m.c2[e];
+            for (int c = 0; c < 3; ++c) P.tri_G[(size_t)c * ne + k] = G0[(size_t)c * ne + e];
+            for (int q = 0; q < nq; ++q) P.conn_soa[(size_t)q * ne + k] = P.node_old2new[P.conn0[e * nq + q]];
+        }
+    }
+    if (m.nvpe == 4) {
+    P.G_soa.resize((size_t)3 * nq * ne);
     P.bilin.resize((size_t)6 * ne);
     for (int64_t k = 0; k < ne; ++k) {
         const int64_t e = P.elem_new2old[k];
@@ -668,6 +730,7 @@ std::string build_plan(const MeshIn& m, const PlanOptions& opt, Plan& P, int& co
             for (int c = 0; c < 3; ++c)
                 P.G_soa[((size_t)c * nq + q) * ne + k] = G0[((size_t)c * nq + q) * ne + e];
         }
+    }
     }
     P.minv.resize(nn);
     for (int64_t i = 0; i < nn; ++i) P.minv[i] = 1.0 / mass[P.node_new2old[i]];

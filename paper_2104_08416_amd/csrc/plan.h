@@ -15,8 +15,9 @@ namespace sem {
 struct MeshIn {
     int64_t nv = 0, ne = 0;
     const double* vxy = nullptr;
-    const int32_t* quad = nullptr;
+    const int32_t* quad = nullptr;    // [ne][nvpe] CCW vertex ids
     const double* c2 = nullptr;
+    int nvpe = 4;                     // vertices per element: 4 quadrilaterals, 3 triangles
 };
 
 struct PlanOptions {
@@ -37,6 +38,7 @@ struct PlanOptions {
 
 struct Plan {
     int p = 0, n = 0, nq = 0;
+    int nvpe = 4;                            // 4 quadrilaterals (GLL tensor), 3 triangles
     int64_t ne = 0, nn = 0, nv = 0;
     double dt = 0.0;
     // 1D GLL ingredients
@@ -69,7 +71,21 @@ struct Plan {
     std::vector<int32_t> colour;
     int32_t n_colours = 0;
     double reorder_seconds = 0.0;
+    // triangles: reference nodes [nq][2], weights [nq], reference matrices [3][nq][nq]
+    // (Sxx, Sxy + Syx, Syy) and per-element factors det J J^-1 J^-T [3][ne] (g11, g12, g22,
+    // new order); dt_from_stability: dt is set to a fraction of the stability limit once
+    // the device power iteration has estimated it
+    std::vector<double> tri_xy, tri_w, tri_S, tri_G;
+    bool dt_from_stability = false;
 };
+
+// Triangles (tri.cpp): local node count, local index of node (i, j), the reference nodes,
+// weights and stiffness matrices, and the original global numbering.
+int tri_nq(int p);
+int tri_lidx(int i, int j, int p);
+std::string tri_reference(int p, const std::vector<double>& gll_x, std::vector<double>& xy,
+                          std::vector<double>& w, std::vector<double>& S);
+std::string tri_number_nodes(const MeshIn& mesh, int p, std::vector<int32_t>& conn, int64_t& nn);
 
 // Fills `plan` or returns a non-empty error string; `code` receives the sem_status.
 std::string build_plan(const MeshIn& mesh, const PlanOptions& opt, Plan& plan, int& code);

@@ -35,7 +35,8 @@ class SemError(RuntimeError):
 
 class _Mesh(ctypes.Structure):
     _fields_ = [("n_vertices", ctypes.c_int64), ("vxy", ctypes.c_void_p),
-                ("n_elements", ctypes.c_int64), ("quad", ctypes.c_void_p), ("c2", ctypes.c_void_p)]
+                ("n_elements", ctypes.c_int64), ("quad", ctypes.c_void_p), ("c2", ctypes.c_void_p),
+                ("vertices_per_element", ctypes.c_int32)]
 
 
 class _Options(ctypes.Structure):
@@ -61,14 +62,14 @@ class _Info(ctypes.Structure):
                 ("setup_seconds", ctypes.c_double), ("reorder_seconds", ctypes.c_double),
                 ("max_accum_nodes", ctypes.c_int32), ("kernel_bytes_per_step", ctypes.c_double),
                 ("n_colours", ctypes.c_int32), ("scatter", ctypes.c_int32),
-                ("growth_per_step", ctypes.c_double)]
+                ("vertices_per_element", ctypes.c_int32), ("growth_per_step", ctypes.c_double)]
 
 
 EXPORTS = ("sem_create", "sem_create_error", "sem_get_info", "sem_get_permutations",
            "sem_get_node_coords", "sem_set_sources", "sem_set_receivers", "sem_set_c2", "sem_reset",
            "sem_run", "sem_step", "sem_get_field", "sem_set_field", "sem_apply_stiffness",
            "sem_adjoint_gradient", "sem_synchronize", "sem_hilbert_index", "sem_last_error",
-           "sem_destroy", "sem_autotune", "sem_get_colours", "sem_apply_stiffness_noalloc")
+           "sem_destroy", "sem_autotune", "sem_get_colours")
 
 
 def _load():
@@ -98,7 +99,6 @@ def _load():
     lib.sem_get_field.argtypes = [P, I32, VP]
     lib.sem_set_field.argtypes = [P, I32, VP]
     lib.sem_apply_stiffness.argtypes = [P, VP, VP]
-    lib.sem_apply_stiffness_noalloc.argtypes = [P, VP, VP]
     lib.sem_adjoint_gradient.argtypes = [P, VP, I64, I32, VP]
     lib.sem_synchronize.argtypes = [P]
     lib.sem_hilbert_index.argtypes = [I64, I64, I64, VP, VP, VP]
@@ -136,6 +136,7 @@ def hilbert_index(W: int, H: int, cx, cy) -> np.ndarray:
 class Simulator:
     """One SEM context (mesh, reorder, geometry, device state).
 
+    ``quads`` is [E, 4] (quadrilaterals) or [E, 3] (the paper's triangles, odd p).
     ``device=-1`` builds a host-only context (setup, permutations, snapping; no compute).
     """
 
@@ -151,7 +152,7 @@ class Simulator:
         self.precision = precision
         self.device = device
         m = _Mesh(self._vxy.shape[0], _ptr(self._vxy), self._quads.shape[0], _ptr(self._quads),
-                  _ptr(self._c2))
+                  _ptr(self._c2), self._quads.shape[1])
         if device >= 0:
             import torch
             if stream is None:
@@ -301,15 +302,6 @@ class Simulator:
         self._check(_lib.sem_apply_stiffness(self._h, u.data_ptr(), r.data_ptr()), "sem_apply_stiffness")
         return r
 
-    def apply_stiffness_noalloc(self, u, r):
-        """r = K u into the caller's tensor r without any device allocation (static scratch;
-        asynchronous on the simulator's stream)."""
-        assert u.is_contiguous() and u.dtype == self.torch_dtype
-        assert r.is_contiguous() and r.dtype == self.torch_dtype and r.shape == u.shape
-        self._check(_lib.sem_apply_stiffness_noalloc(self._h, u.data_ptr(), r.data_ptr()),
-                    "sem_apply_stiffness_noalloc")
-        return r
-
     def adjoint_gradient(self, dL_dtraces, nsteps: int, ckpt_every: int = 40):
         import torch
         assert dL_dtraces.is_contiguous() and dL_dtraces.dtype == self.torch_dtype
@@ -384,7 +376,7 @@ def autotune(vxy, quads, c2, p: int, precision: str = "f32", order: str = "hilbe
     if stream is None:
         with torch.cuda.device(device):
             stream = torch.cuda.current_stream(device).cuda_stream
-    m = _Mesh(vxy.shape[0], _ptr(vxy), quads.shape[0], _ptr(quads), _ptr(c2))
+    m = _Mesh(vxy.shape[0], _ptr(vxy), quads.shape[0], _ptr(quads), _ptr(c2), quads.shape[1])
     f = dict(fixed)
     o = _Options(p, F64 if precision == "f64" else F32, ORDERS[order], NODE_ORDERS["first_touch"],
                  f.pop("seed", 3), n_shots, device, f.pop("dt", 0.0), f.pop("cfl", 0.3), stream or 0,

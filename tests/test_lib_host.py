@@ -247,3 +247,38 @@ def test_scatter_options(semlib):
             semlib.Simulator(wl.vxy, wl.quads, wl.c2, wl.p, device=-1, scatter="bogus")
     finally:
         del semlib.SCATTERS["bogus"]
+
+
+@pytest.mark.parametrize("p", [1, 3, 5, 7])
+def test_triangle_setup_matches_oracle(semlib, p):
+    """Triangles (the paper's element, Sec. 4.2): node count, original numbering through the
+    node coordinates, and the element and node permutations of every order bit-exact against
+    the oracle; the colours are the oracle's first-fit colours."""
+    from oracle import colour, triangle
+    wl = workloads.workload("tri2000", n=14, p=p)
+    conn, nn = triangle.global_numbering(wl.quads, wl.vxy.shape[0], p)
+    xy_o = triangle.node_coordinates(wl.vxy, wl.quads, conn, p)
+    for kind in ("hilbert", "morton", "lex", "random", "connectivity", "distance"):
+        s = semlib.Simulator(wl.vxy, wl.quads, wl.c2, p, order=kind, device=-1, seed=3)
+        assert s.n_nodes == nn
+        assert s.info()["vertices_per_element"] == 3
+        np.testing.assert_allclose(s.node_coords(), xy_o, rtol=0, atol=1e-12)
+        e, n = s.permutations()
+        oe, on = reorder.reorder(kind, wl.vxy, wl.quads, conn, seed=3)
+        np.testing.assert_array_equal(e, oe, err_msg=kind)
+        np.testing.assert_array_equal(n, on, err_msg=kind)
+        np.testing.assert_array_equal(s.colours(), colour.greedy_colours(conn, e), err_msg=kind)
+        s.close()
+
+
+def test_triangle_options_refused(semlib):
+    wl = workloads.workload("tri2000", n=6)
+    for kw in (dict(p=4), dict(p=5, formulation="heun"), dict(p=5, scatter="colour")):
+        p = kw.pop("p")
+        with pytest.raises(semlib.SemError) as ei:
+            semlib.Simulator(wl.vxy, wl.quads, wl.c2, p, device=-1, **kw)
+        assert ei.value.status in ("INVALID_ARG", "BAD_MESH"), kw
+    cw = wl.quads[:, ::-1].copy()                       # clockwise triangles
+    with pytest.raises(semlib.SemError) as ei:
+        semlib.Simulator(wl.vxy, cw, wl.c2, 5, device=-1)
+    assert ei.value.status == "BAD_MESH"

@@ -195,3 +195,16 @@ def test_node_spacing_cfl_does_not_bound_the_spectrum():
     sem = triangle.TriSEM(vxy, tris, np.ones(tris.shape[0]), 7)
     assert sem.dt_cfl(0.3) > 2.0 / np.sqrt(sem.lambda_max())
     assert sem.dt_default() < 2.0 / np.sqrt(sem.lambda_max())
+
+
+def test_sampled_rows_match_assembly():
+    """The per-node checker of the full-size GPU tests equals rows of the assembled K and
+    the lumped mass (corner, edge, interior and vertex nodes, jittered mesh, variable c)."""
+    vxy, tris, _, _ = workloads.tri_mesh(7, 5, 700.0, 500.0, jitter=0.2, seed=8)
+    c2 = np.random.default_rng(2).uniform(1.0, 3.0, tris.shape[0]) * 1e6
+    sem = triangle.TriSEM(vxy, tris, c2, 5)
+    u = np.random.default_rng(3).standard_normal(sem.n_nodes)
+    nodes = np.unique(np.r_[0, 7, 40, sem.n_nodes - 1, np.random.default_rng(4).choice(sem.n_nodes, 40, replace=False)])
+    r, M = triangle.sampled_rows(vxy, tris, c2, 5, sem.conn, nodes, u)
+    np.testing.assert_allclose(r, (sem.K @ u)[nodes], rtol=1e-13, atol=1e-13 * np.abs(sem.K @ u).max())
+    np.testing.assert_allclose(M, sem.mass[nodes], rtol=1e-13)
