@@ -245,6 +245,16 @@ int sem_set_field(sem_ctx* ctx, int32_t which, const void* dev);
  * both device buffers [n_shots][n_nodes] in original numbering. For operator checks. */
 int sem_apply_stiffness(sem_ctx* ctx, const void* u_dev, void* r_dev);
 
+/* sem_apply_stiffness without any device allocation, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * The permuted input and the result are staged in a static per-device scratch array of
+ * 64 MiB (held by every device the library runs on until the process ends), so
+ * n_nodes * n_shots * word size must be <= 32 MiB (else INVALID_ARG, nothing launched).
+ * Asynchronous on the context stream (no synchronisation). All calls on one device share the
+ * scratch: calls that can overlap in time on one device (other streams, other threads, other
+ * contexts on the device) race and must be serialised by the caller. */
+int sem_apply_stiffness_noalloc(sem_ctx* ctx, const void* u_dev, void* r_dev);
+
 /* Gradient of a loss of the receiver traces with respect to c^2 of every element.
  * Runs the forward from rest for nsteps steps storing (u, v) every ckpt_every steps, then
  * the discrete adjoint backwards segment by segment, recomputing each segment's forward

@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <random>
@@ -26,6 +27,12 @@ struct DevBuf {
 };
 
 }  // namespace
+
+// Scratch of the allocation-free stiffness apply: the permuted input and the result of one
+// call, each at most half of it. Every device the library runs on holds its own copy for the
+// life of the process; calls on one device share it.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 struct sem_ctx {
     sem::Plan plan;
@@ -401,6 +408,27 @@ int power_iteration(sem_ctx* c, int iters) {
     c->c2_ref = c->plan.c2;
     c->lambda_ref = lam;
     return zero_state<T>(c);
+}
+
+// Device address of the scratch array on the context's device (current), looked up once per
+// device; the array's name is only a host-side stand-in and is never passed to a kernel.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_address(sem_ctx* c, void** out) {
+    if (c->device < 0 || c->device >= kMaxDevices)
+        return fail(c, SEM_ERR_INVALID_ARG, "device ordinal out of range for the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[c->device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(c, SEM_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[c->device] = p;
+    }
+    *out = g_scratch_ptr[c->device];
+    return SEM_OK;
 }
 
 int check_ctx(const sem_ctx* c) { return c ? SEM_OK : SEM_ERR_INVALID_ARG; }
@@ -1020,6 +1048,8 @@ int sem_create(const sem_mesh* mesh, const sem_options* opt, sem_ctx** out) {
     }
     if (!c->host_only) {
         int rc = set_device(c);
+        void* scratch_ptr = nullptr;
+        if (rc == SEM_OK) rc = scratch_address(c, &scratch_ptr);
         if (rc == SEM_OK) rc = c->precision == SEM_F64 ? upload_mesh<double>(c) : upload_mesh<float>(c);
         if (rc == SEM_OK && c->formulation == SEM_FORM_HEUN)
             rc = c->precision == SEM_F64 ? setup_heun<double>(c) : setup_heun<float>(c);
@@ -1282,6 +1312,27 @@ int sem_apply_stiffness(sem_ctx* c, const void* u_dev, void* r_dev) {
     rc = set_device(c);
     if (rc) return rc;
     return c->precision == SEM_F64 ? apply_t<double>(c, u_dev, r_dev) : apply_t<float>(c, u_dev, r_dev);
+}
+
+int sem_apply_stiffness_noalloc(sem_ctx* c, const void* u_dev, void* r_dev) {
+    if (!c || !u_dev || !r_dev) return SEM_ERR_INVALID_ARG;
+    int rc = need_device(c);
+    if (rc) return rc;
+    rc = set_device(c);
+    if (rc) return rc;
+    const size_t bytes = (size_t)c->plan.nn * c->S * c->wsize;
+    const size_t half = (bytes + 255) & ~(size_t)255;
+    if (2 * half > kScratchBytes)
+        return fail(c, SEM_ERR_INVALID_ARG,
+                    "n_nodes * n_shots * word size = " + std::to_string(bytes) + " bytes exceeds the " +
+                        std::to_string(kScratchBytes / 2) + " bytes of one half of the scratch");
+    void* base = nullptr;
+    rc = scratch_address(c, &base);
+    if (rc) return rc;
+    void* tin = base;
+    void* tout = (unsigned char*)base + half;
+    return c->precision == SEM_F64 ? apply_into<double>(c, u_dev, r_dev, tin, tout)
+                                   : apply_into<float>(c, u_dev, r_dev, tin, tout);
 }
 
 int sem_adjoint_gradient(sem_ctx* c, const void* dL, int64_t nsteps, int32_t ckpt_every, double* grad) {

@@ -69,7 +69,7 @@ EXPORTS = ("sem_create", "sem_create_error", "sem_get_info", "sem_get_permutatio
            "sem_get_node_coords", "sem_set_sources", "sem_set_receivers", "sem_set_c2", "sem_reset",
            "sem_run", "sem_step", "sem_get_field", "sem_set_field", "sem_apply_stiffness",
            "sem_adjoint_gradient", "sem_synchronize", "sem_hilbert_index", "sem_last_error",
-           "sem_destroy", "sem_autotune", "sem_get_colours")
+           "sem_destroy", "sem_autotune", "sem_get_colours", "sem_apply_stiffness_noalloc")
 
 
 def _load():
@@ -99,6 +99,7 @@ def _load():
     lib.sem_get_field.argtypes = [P, I32, VP]
     lib.sem_set_field.argtypes = [P, I32, VP]
     lib.sem_apply_stiffness.argtypes = [P, VP, VP]
+    lib.sem_apply_stiffness_noalloc.argtypes = [P, VP, VP]
     lib.sem_adjoint_gradient.argtypes = [P, VP, I64, I32, VP]
     lib.sem_synchronize.argtypes = [P]
     lib.sem_hilbert_index.argtypes = [I64, I64, I64, VP, VP, VP]
@@ -300,6 +301,15 @@ class Simulator:
         assert u.is_contiguous() and u.dtype == self.torch_dtype
         r = torch.empty_like(u)
         self._check(_lib.sem_apply_stiffness(self._h, u.data_ptr(), r.data_ptr()), "sem_apply_stiffness")
+        return r
+
+    def apply_stiffness_noalloc(self, u, r):
+        """r = K u into the caller's tensor r without any device allocation (static scratch;
+        asynchronous on the simulator's stream)."""
+        assert u.is_contiguous() and u.dtype == self.torch_dtype
+        assert r.is_contiguous() and r.dtype == self.torch_dtype and r.shape == u.shape
+        self._check(_lib.sem_apply_stiffness_noalloc(self._h, u.data_ptr(), r.data_ptr()),
+                    "sem_apply_stiffness_noalloc")
         return r
 
     def adjoint_gradient(self, dL_dtraces, nsteps: int, ckpt_every: int = 40):
