@@ -274,16 +274,18 @@ int sem_hilbert_index(int64_t W, int64_t H, int64_t n, const int64_t* cx, const 
 
 /* Launch-configuration autotuner. Times the step kernel of every candidate configuration
  * on this mesh and returns the fastest. Only fields of *base that are zero vary:
- *   n_shots == 1:        block_threads in {256, 512, 1024};
+ *   n_shots == 1 or triangles: block_threads in {256, 512, 1024} x tile_items in {1, 2}
+ *                        workgroup passes (quadrilaterals) or {4, 8, 16} (triangles), a pass
+ *                        being 64 / (p+1) (64 / nodes per triangle) elements per wave;
  *   n_shots % 64 == 0:   block_threads in {256, 512} x lds_bytes in {24, 32, 48, 64} KB;
  *   other shot batches:  shot_lanes in {1, 2, 4, 8, 16} (those dividing n_shots).
  * Each candidate runs the full sem_create (setup, dt check), `warmup` untimed steps and
  * `steps` timed steps (HIP events on base->stream, no sources or receivers), then is
  * destroyed. base->device must be a device ordinal. On return *best holds *base with the
  * winning fields filled in and *best_us its time per step; table (may be NULL) receives
- * up to table_cap rows of 4 doubles (block_threads, shot_lanes, lds_bytes, us per step,
- * -1 for a candidate whose setup failed) and *n_tried (may be NULL) the number of
- * candidates. Errors: INVALID_ARG, NO_DEVICE (device < 0), or the error of sem_create
+ * up to table_cap rows of 5 doubles (block_threads, shot_lanes, lds_bytes, tile_items, us
+ * per step, -1 for a candidate whose setup failed) and *n_tried (may be NULL) the number
+ * of candidates. Errors: INVALID_ARG, NO_DEVICE (device < 0), or the error of sem_create
  * when no candidate could be built. */
 int sem_autotune(const sem_mesh* mesh, const sem_options* base, int32_t warmup, int32_t steps,
                  sem_options* best, double* best_us, double* table, int32_t table_cap,

@@ -968,9 +968,11 @@ int sem_create(const sem_mesh* mesh, const sem_options* opt, sem_ctx** out) {
     po.tile_items = pick_tile_items(opt->p, c->SL, row_block, opt->tile_items);
     if (opt->tile_items <= 0 && c->SL == 1) po.tile_items = epb;
     if (nvpe == 3 && opt->tile_items <= 0) {
-        // triangles: several passes of 64 / nq elements per wave, about 96 elements a tile
+        // triangles: eight passes of 64 / nq elements per wave (measured on the 250k-triangle
+        // p = 5 mesh: 192 elements a tile with 512 threads ran 26% faster than 96 and 27%
+        // faster than 384)
         const int epb_tri = (64 / sem::tri_nq(opt->p)) * (row_block / 64);
-        po.tile_items = std::max(1, (96 + epb_tri - 1) / epb_tri) * epb_tri;
+        po.tile_items = 8 * epb_tri;
     }
     // 64 shots: tiles are bounded by the LDS accumulator, not by an element count
     if (opt->tile_items <= 0 && c->SL == 64) po.tile_items = 1 << 20;
@@ -1388,8 +1390,20 @@ int sem_autotune(const sem_mesh* mesh, const sem_options* base, int32_t warmup, 
         for (int bt : bts) { o.block_threads = bt; cand.push_back(o); }
     };
     const int S = base->n_shots;
-    if (S == 1) {
-        vary_threads({256, 512, 1024}, *base);
+    const bool tri = mesh->vertices_per_element == 3;
+    if (S == 1 || tri) {
+        // workgroup size x tile size (own + halo elements, in workgroup passes of
+        // 64 / nodes-per-element-row elements per wave)
+        const int per_wave = tri ? 64 / sem::tri_nq(base->p) : 64 / (base->p + 1);
+        const std::vector<int> passes = tri ? std::vector<int>{4, 8, 16} : std::vector<int>{1, 2};
+        std::vector<int> bts = {256, 512, 1024};
+        if (base->block_threads > 0) bts = {base->block_threads};
+        for (int bt : bts) {
+            sem_options o = *base;
+            o.block_threads = bt;
+            if (base->tile_items > 0 || base->tile_elems > 0) { cand.push_back(o); continue; }
+            for (int np : passes) { o.tile_items = np * per_wave * (bt / 64); cand.push_back(o); }
+        }
     } else if (S % 64 == 0 && (base->shot_lanes == 0 || base->shot_lanes == 64)) {
         sem_options o = *base;
         if (o.lds_bytes > 0) {
@@ -1444,10 +1458,11 @@ int sem_autotune(const sem_mesh* mesh, const sem_options* base, int32_t warmup, 
             best_t = us;
         }
         if (table && (int32_t)k < table_cap) {
-            table[4 * k + 0] = cand[k].block_threads;
-            table[4 * k + 1] = cand[k].shot_lanes;
-            table[4 * k + 2] = cand[k].lds_bytes;
-            table[4 * k + 3] = us;
+            table[5 * k + 0] = cand[k].block_threads;
+            table[5 * k + 1] = cand[k].shot_lanes;
+            table[5 * k + 2] = cand[k].lds_bytes;
+            table[5 * k + 3] = cand[k].tile_items;
+            table[5 * k + 4] = us;
         }
     }
     (void)hipEventDestroy(ev0);

@@ -376,8 +376,8 @@ def autotune(vxy, quads, c2, p: int, precision: str = "f32", order: str = "hilbe
              device: int = 0, warmup: int = 3, steps: int = 20, stream=None, **fixed):
     """Time the step kernel over the library's candidate launch configurations (see
     sem_autotune) and return (best, table): ``best`` holds the Simulator keyword arguments
-    of the fastest (block_threads, shot_lanes, lds_bytes, us_per_step); ``table`` one dict
-    per candidate. Keyword arguments in ``fixed`` (block_threads, shot_lanes, lds_bytes,
+    of the fastest (block_threads, shot_lanes, lds_bytes, tile_items, us_per_step); ``table``
+    one dict per candidate. Keyword arguments in ``fixed`` (block_threads, shot_lanes, lds_bytes,
     tile_items, tile_elems, dt, cfl, seed) are held fixed."""
     import torch
     vxy = np.ascontiguousarray(vxy, dtype=np.float64)
@@ -396,16 +396,16 @@ def autotune(vxy, quads, c2, p: int, precision: str = "f32", order: str = "hilbe
         raise TypeError(f"unknown fixed options {sorted(f)}")
     best = _Options()
     best_us = ctypes.c_double()
-    table = np.zeros((64, 4), np.float64)
+    table = np.zeros((64, 5), np.float64)
     n = ctypes.c_int32()
     rc = _lib.sem_autotune(ctypes.byref(m), ctypes.byref(o), warmup, steps, ctypes.byref(best),
                            ctypes.byref(best_us), _ptr(table), table.shape[0], ctypes.byref(n))
     if rc:
         raise SemError(rc, _lib.sem_create_error().decode())
-    rows = [dict(block_threads=int(r[0]), shot_lanes=int(r[1]), lds_bytes=int(r[2]), us_per_step=float(r[3]))
-            for r in table[:min(n.value, table.shape[0])]]
+    rows = [dict(block_threads=int(r[0]), shot_lanes=int(r[1]), lds_bytes=int(r[2]), tile_items=int(r[3]),
+                 us_per_step=float(r[4])) for r in table[:min(n.value, table.shape[0])]]
     return (dict(block_threads=best.block_threads, shot_lanes=best.shot_lanes, lds_bytes=best.lds_bytes,
-                 us_per_step=best_us.value), rows)
+                 tile_items=best.tile_items, us_per_step=best_us.value), rows)
 
 
 def sem_forward(c2, sim: Simulator, nsteps: int, ckpt_every: int = 40):

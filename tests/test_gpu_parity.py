@@ -314,10 +314,12 @@ def test_autotune_picks_a_timed_candidate(semlib, gpu_ok, shots):
     say("case autotune", shots)
     wl = workloads.workload("batch512", n=32, n_shots=shots, nsteps=60)
     best, rows = semlib.autotune(wl.vxy, wl.quads, wl.c2, wl.p, precision="f32", n_shots=shots, steps=10)
-    assert len(rows) == (3 if shots == 1 else 8)
+    assert len(rows) == (6 if shots == 1 else 8)
     assert all(r["us_per_step"] > 0 for r in rows)
     assert best["us_per_step"] == min(r["us_per_step"] for r in rows)
-    kw = {k: best[k] for k in ("block_threads", "lds_bytes")}
+    if shots == 1:
+        assert len({r["tile_items"] for r in rows}) == 4      # 2 tile sizes x 3 workgroup sizes
+    kw = {k: best[k] for k in ("block_threads", "lds_bytes", "tile_items")}
     out = []
     for opts in (kw, {}):
         s = semlib.Simulator(wl.vxy, wl.quads, wl.c2, wl.p, precision="f32", n_shots=shots, **opts)
