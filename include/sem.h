@@ -76,11 +76,15 @@ enum sem_formulation { SEM_FORM_LEAPFROG = 0, SEM_FORM_HEUN = 1 };
  *     order (two elements sharing a node differ in colour), one launch per colour adds
  *     r_e into a global r with plain read-modify-write (no two elements of a colour share
  *     a node), then one launch applies the update and clears r.
- *   SEM_SCATTER_ATOMIC: one launch over all elements adds r_e into a global r with global
- *     floating-point atomics, then the update launch.
+ *   SEM_SCATTER_ATOMIC: single shot: one launch over all elements adds r_e into a global r
+ *     with global floating-point atomics, then the update launch. Batches of 64-shot lanes:
+ *     tiles process their own elements only (no halo); nodes whose elements all lie in the
+ *     tile are summed in LDS, border nodes take -dt/M r_e on their 64-shot rows of v with
+ *     global atomics, and a border pass after the step forms their u.
  *   SEM_SCATTER_AUTO: the fastest measured on MI355X for the context's kernel, which is
  *     LDS_ATOMIC for every configuration measured so far.
- * COLOUR and ATOMIC are built for the single-shot leapfrog step (n_shots = 1). */
+ * COLOUR is built for the single-shot leapfrog step on quadrilaterals, ATOMIC for that step
+ * and for batches of 64-shot lanes. */
 enum sem_scatter { SEM_SCATTER_AUTO = 0, SEM_SCATTER_LDS_ATOMIC = 1, SEM_SCATTER_COLOUR = 2,
                    SEM_SCATTER_ATOMIC = 3 };
 

@@ -77,6 +77,11 @@ struct sem_ctx {
     // launch ranges of the element arrays (one per colour; [0, E) for ATOMIC)
     DevBuf racc, src_node, rec_node;
     DevBuf tri_S;                     // triangles: reference matrices [3][nq][nq]
+    // 64-shot atomic scatter: owned border nodes per tile, all border nodes, and the
+    // receivers at border nodes (receiver index, node)
+    DevBuf tile_nbd, border_nodes, brec_idx, brec_node;
+    int32_t n_brec = 0;
+    bool border = false;
     std::vector<int32_t> elem_slot;
     std::vector<int64_t> ranges;
 };
@@ -152,6 +157,7 @@ sem::StepArgs<T> base_args(sem_ctx* c) {
     a.tile_eb = (const int32_t*)c->tile_eb.p;
     a.tile_nb = (const int32_t*)c->tile_nb.p;
     a.tile_ns = (const int32_t*)c->tile_ns.p;
+    a.tile_nbd = c->border ? (const int32_t*)c->tile_nbd.p : nullptr;
     a.halo_b = (const int32_t*)c->halo_b.p;
     a.halo = (const int32_t*)c->halo.p;
     a.n_slices = c->S / c->SL;
@@ -178,6 +184,7 @@ size_t lds_bytes(const sem_ctx* c) {
 }
 
 bool row_kernel(const sem_ctx* c);
+bool shots_kernel(const sem_ctx* c);
 bool shot_major(const sem_ctx* c);
 
 // One step-kernel launch over all tiles. The row kernel (one shot lane) keeps the state
@@ -216,8 +223,20 @@ int global_launch(sem_ctx* c, const sem::StepArgs<T>& a0) {
 
 template <typename T>
 int launch(sem_ctx* c, const sem::StepArgs<T>& a) {
-    if (c->scatter != SEM_SCATTER_LDS_ATOMIC) return global_launch<T>(c, a);
+    if (c->scatter != SEM_SCATTER_LDS_ATOMIC && !shots_kernel(c)) return global_launch<T>(c, a);
     const int64_t nt = (int64_t)c->plan.tile_eb.size() - 1;
+    if (c->border) {
+        // 64 shots, atomic scatter: border rows of r_out are sums of atomics (modes 1, 2), and
+        // border nodes take u_out in a pass after the step launch (mode 0)
+        if (a.mode != 0)
+            SEM_HIP(c, sem::launch_fill<T>(a.r_out, T(0), c->plan.nn * (int64_t)c->S, c->stream));
+        SEM_HIP(c, sem::launch_step<T>(c->plan.p, c->SL, c->geo, nt, lds_bytes(c), a, c->stream));
+        if (a.mode == 0)
+            SEM_HIP(c, sem::launch_border<T>(a, (const int32_t*)c->border_nodes.p,
+                                             (int64_t)c->plan.border_nodes.size(), (const int32_t*)c->brec_idx.p,
+                                             (const int32_t*)c->brec_node.p, c->n_brec, c->stream));
+        return SEM_OK;
+    }
     if (!shot_major(c) || c->S == 1) {
         SEM_HIP(c, sem::launch_step<T>(c->plan.p, c->SL, c->geo, nt, lds_bytes(c), a, c->stream));
         return SEM_OK;
@@ -544,6 +563,10 @@ int upload_mesh(sem_ctx* c) {
     SEM_HIP(c, upload(c, c->tile_eb, P.tile_eb));
     SEM_HIP(c, upload(c, c->tile_nb, P.tile_nb));
     if (!P.tile_ns.empty()) SEM_HIP(c, upload(c, c->tile_ns, P.tile_ns));
+    if (c->border) {
+        SEM_HIP(c, upload(c, c->tile_nbd, P.tile_nbd));
+        SEM_HIP(c, upload(c, c->border_nodes, P.border_nodes.empty() ? std::vector<int32_t>{0} : P.border_nodes));
+    }
     SEM_HIP(c, upload(c, c->halo_b, P.halo_b));
     std::vector<int32_t> h = P.halo;
     if (h.empty()) h.push_back(0);
@@ -692,6 +715,17 @@ int set_receivers_t(sem_ctx* c, int32_t n, const double* xy, int32_t* node_out) 
     SEM_HIP(c, upload(c, c->rec_loc, loc.empty() ? std::vector<int32_t>{0} : loc));
     SEM_HIP(c, upload(c, c->rec_idx, idx.empty() ? std::vector<int32_t>{0} : idx));
     SEM_HIP(c, upload(c, c->rec_node, node.empty() ? std::vector<int32_t>{0} : node));
+    if (c->border) {
+        std::vector<int32_t> bi, bn;
+        for (const Ent& e : ents)
+            if (e.loc >= P.tile_ns[e.tile] && e.loc < P.tile_ns[e.tile] + P.tile_nbd[e.tile]) {
+                bi.push_back(e.r);
+                bn.push_back(P.tile_nb[e.tile] + e.loc);
+            }
+        c->n_brec = (int32_t)bi.size();
+        SEM_HIP(c, upload(c, c->brec_idx, bi.empty() ? std::vector<int32_t>{0} : bi));
+        SEM_HIP(c, upload(c, c->brec_node, bn.empty() ? std::vector<int32_t>{0} : bn));
+    }
     return SEM_OK;
 }
 
@@ -936,11 +970,16 @@ int sem_create(const sem_mesh* mesh, const sem_options* opt, sem_ctx** out) {
     // AUTO: owner-tile LDS accumulation, measured fastest for every kernel (colour passes
     // and global atomics both move r through L2 and HBM)
     c->scatter = opt->scatter == SEM_SCATTER_AUTO ? SEM_SCATTER_LDS_ATOMIC : opt->scatter;
-    if (c->scatter != SEM_SCATTER_LDS_ATOMIC && (c->S != 1 || opt->formulation != SEM_FORM_LEAPFROG || nvpe != 4)) {
-        g_create_error = "the COLOUR and ATOMIC scatters run the single-shot leapfrog step on quadrilaterals";
+    const bool shots64 = c->S % 64 == 0 && c->SL == 64;
+    if (c->scatter != SEM_SCATTER_LDS_ATOMIC &&
+        (opt->formulation != SEM_FORM_LEAPFROG || nvpe != 4 ||
+         !(c->S == 1 || (shots64 && c->scatter == SEM_SCATTER_ATOMIC)))) {
+        g_create_error = "COLOUR runs the single-shot leapfrog step on quadrilaterals, ATOMIC that step or "
+                         "batches of 64-shot lanes";
         delete c;
         return SEM_ERR_INVALID_ARG;
     }
+    c->border = shots64 && c->scatter == SEM_SCATTER_ATOMIC;
     sem::PlanOptions po;
     po.p = opt->p;
     po.elem_order = opt->elem_order;
@@ -980,6 +1019,7 @@ int sem_create(const sem_mesh* mesh, const sem_options* opt, sem_ctx** out) {
     while (np < max_np && np * epb < (opt->tile_elems > 0 ? opt->tile_elems : po.tile_items)) np *= 2;
     po.max_owned = pick_max_owned(c->SL, opt->precision, opt->lds_bytes);
     po.split_single = c->S > 1 && c->SL == 64;
+    po.border = c->border;
     if (po.max_owned < 1) {
         g_create_error = "lds_bytes too small for one owned node";
         delete c;
@@ -1486,7 +1526,8 @@ void sem_destroy(sem_ctx* c) {
                           &c->halo, &c->n2o_node, &c->n2o_elem, &c->u[0], &c->u[1], &c->v,
                           &c->src_b, &c->src_loc, &c->src_shot, &c->src_w, &c->rec_b, &c->rec_loc,
                           &c->rec_idx, &c->u_next, &c->hv[0], &c->hv[1], &c->minv_w, &c->u_pred,
-                          &c->racc, &c->src_node, &c->rec_node, &c->tri_S};
+                          &c->racc, &c->src_node, &c->rec_node, &c->tri_S, &c->tile_nbd,
+                          &c->border_nodes, &c->brec_idx, &c->brec_node};
         for (DevBuf* b : bufs) dev_free(*b);
     }
     delete c;

@@ -35,6 +35,8 @@ struct StepArgs {
     const int32_t* tile_nb;   // [T+1] owned node range of each tile
     const int32_t* tile_ns;   // [T] 64-shot kernel: owned nodes of two or more elements
                               //     (the first tile_ns[t] of the range; the rest have one)
+    const int32_t* tile_nbd;  // [T] 64-shot atomic scatter: owned border nodes, right after
+                              //     the tile_ns[t] internal ones (null otherwise)
     const int32_t* halo_b;    // [T+1]
     const int32_t* halo;      // halo elements of all tiles
     int32_t n_slices;         // S / shot_lanes
@@ -92,6 +94,12 @@ hipError_t launch_elems(int p, int threads, bool atomic, const StepArgs<T>& a, h
 // mode 0: v -= dt M^-1 r, u_out = u_in + dt v; mode 1: r_out = r; mode 2: r_out = dt M^-1 r.
 template <typename T>
 hipError_t launch_node_update(const StepArgs<T>& a, int64_t n, hipStream_t stream);
+// Border pass of the 64-shot atomic scatter (after the step launch, mode 0): u_out = u_in +
+// dt v on the rows of the n_nodes border nodes; then traces of the n_rec receivers at border
+// nodes (rec_idx, rec_node) when a.trace is set.
+template <typename T>
+hipError_t launch_border(const StepArgs<T>& a, const int32_t* nodes, int64_t n_nodes, const int32_t* rec_idx,
+                         const int32_t* rec_node, int32_t n_rec, hipStream_t stream);
 // Point terms of the global-accumulator step. phase 0 (before the element launches):
 // racc -= source amplitudes at src_node (shot a.shot) and adjoint injections at rec_node;
 // phase 1 (after the node pass): traces from u_out at rec_node.

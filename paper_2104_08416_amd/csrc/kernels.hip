@@ -345,7 +345,12 @@ __device__ __forceinline__ double rlane<double>(double v, int l) {
     return __hiloint2double(hi, lo);
 }
 
-template <typename T, int P, int BT>
+// BORDER (scatter ATOMIC): tiles process their own elements only. Owned nodes whose elements
+// all lie in the tile are summed in LDS as above; a border node (touched by another tile's
+// elements) receives -dt/M c^2 (K_e u_e) from every element through global FP atomics on its
+// 64-shot row of v (r_out in modes 1, 2), and border_update_kernel forms its u_out after the
+// launch. No halo element is recomputed and no halo row gathered.
+template <typename T, int P, int BT, bool BORDER>
 __global__ void __launch_bounds__(BT) step_shots_kernel(const StepArgs<T> a) {
     constexpr int N = P + 1, NQ = N * N, SL = 64, NW = BT / 64;
     constexpr int NI = (P - 1) * (P - 1);              // element-interior nodes
@@ -363,11 +368,13 @@ __global__ void __launch_bounds__(BT) step_shots_kernel(const StepArgs<T> a) {
     const int s0 = (logical - tile * a.n_slices) * SL;
     const int nb = a.tile_nb[tile];
     const int nown = a.tile_nb[tile + 1] - nb;
-    const int ns = a.tile_ns[tile];                     // owned nodes of >= 2 elements
+    const int ns = a.tile_ns[tile];                     // owned nodes of >= 2 elements (BORDER:
+                                                        // of >= 2 elements all in this tile)
+    const int nbd = BORDER ? a.tile_nbd[tile] : 0;     // BORDER: owned border nodes, after those
     const int eb = a.tile_eb[tile];
     const int n_own_el = a.tile_eb[tile + 1] - eb;
     const int hb = a.halo_b[tile];
-    const int n_items = n_own_el + (a.halo_b[tile + 1] - hb);
+    const int n_items = n_own_el + (BORDER ? 0 : a.halo_b[tile + 1] - hb);
     const int S = a.S;
     const cptr<int32_t> halo = as_const(a.halo);
     const cptr<T> dtminv = as_const(a.dtminv);
@@ -488,6 +495,12 @@ __global__ void __launch_bounds__(BT) step_shots_kernel(const StepArgs<T> a) {
             const int loc = node - nb;
             if ((unsigned)loc < (unsigned)ns) {
                 atomicAdd(&acc[loc * SL + lane], (double)(c2 * r[q]));
+            } else if (BORDER && ((unsigned)(loc - ns) < (unsigned)nbd || (unsigned)loc >= (unsigned)nown)) {
+                // a border node, this tile's or another's: its sum completes after every tile
+                const T rt = c2 * r[q];
+                const int64_t g = (int64_t)node * S + s0 + lane;
+                if (a.mode == 0) atomicAdd(&a.v[g], -(dtminv[node] * rt));
+                else atomicAdd(&a.r_out[g], a.mode == 2 ? dtminv[node] * rt : rt);
             } else if (own && (unsigned)loc < (unsigned)nown) {
                 // a node on the domain boundary that only this element touches
                 const T rt = c2 * r[q];
@@ -539,6 +552,8 @@ __global__ void __launch_bounds__(BT) step_shots_kernel(const StepArgs<T> a) {
             const T f = a.src_w[i] * amp;
             if (loc < ns) {
                 atomicAdd(&acc[loc * SL + sh], -(double)f);
+            } else if (BORDER && loc < ns + nbd) {
+                atomicAdd(&a.v[(int64_t)(nb + loc) * S + s0 + sh], a.dtminv[nb + loc] * f);
             } else {
                 const int64_t g = (int64_t)(nb + loc) * S + s0 + sh;
                 const T dv = a.dtminv[nb + loc] * f;
@@ -555,6 +570,8 @@ __global__ void __launch_bounds__(BT) step_shots_kernel(const StepArgs<T> a) {
                         a.inj_scale;
             if (loc < ns) {
                 atomicAdd(&acc[loc * SL + sh], -(double)f);
+            } else if (BORDER && loc < ns + nbd) {
+                atomicAdd(&a.v[(int64_t)(nb + loc) * S + s0 + sh], a.dtminv[nb + loc] * f);
             } else {
                 const int64_t g = (int64_t)(nb + loc) * S + s0 + sh;
                 const T dv = a.dtminv[nb + loc] * f;
@@ -594,6 +611,7 @@ __global__ void __launch_bounds__(BT) step_shots_kernel(const StepArgs<T> a) {
             __syncthreads();
             for (int i = threadIdx.x; i < (re - rb) * SL; i += BT) {
                 const int kk = rb + i / SL, sh = i % SL, loc = a.rec_loc[kk];
+                if (BORDER && loc >= ns && loc < ns + nbd) continue;    // recorded after the border pass
                 // single-element nodes: read back from L2 (the corrections above are atomics)
                 a.trace[((int64_t)(s0 + sh) * a.n_rec + a.rec_idx[kk]) * a.trace_cols + a.trace_col] =
                     loc < ns ? (T)acc[loc * SL + sh]
@@ -1320,7 +1338,7 @@ hipError_t launch_rows(int64_t n_tiles, size_t lds, const StepArgs<T>& a, hipStr
 
 template <typename T, int P, int BT>
 hipError_t launch_shots(int64_t n_tiles, size_t lds, const StepArgs<T>& a, hipStream_t st) {
-    auto fn = step_shots_kernel<T, P, BT>;
+    auto fn = a.tile_nbd != nullptr ? step_shots_kernel<T, P, BT, true> : step_shots_kernel<T, P, BT, false>;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -1609,6 +1627,31 @@ hipError_t launch_heun_p(int mode, int64_t n_tiles, size_t lds, const HeunArgs<T
     return hipGetLastError();
 }
 
+// Border pass of the 64-shot atomic scatter: every border node's v is complete once the
+// step launch has ended; u_out = u_in + dt v on its rows (one wave per node and 64-shot slice),
+// then the traces of receivers at border nodes.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) border_update_kernel(const StepArgs<T> a, const int32_t* nodes,
+                                                               int64_t n_nodes) {
+    const int lane = threadIdx.x & 63;
+    const int64_t nw = (int64_t)gridDim.x * (kBlock / 64);
+    const int64_t items = n_nodes * a.n_slices;
+    for (int64_t k = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6; k < items; k += nw) {
+        const int64_t node = nodes[k / a.n_slices];
+        const int64_t g = node * a.S + (k % a.n_slices) * 64 + lane;
+        a.u_out[g] = a.u_in[g] + a.dt * a.v[g];
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) border_trace_kernel(const StepArgs<T> a, const int32_t* rec_idx,
+                                                              const int32_t* rec_node, int32_t n) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= (int64_t)n * a.S) return;
+    const int64_t k = i / a.S, s = i % a.S;
+    a.trace[(s * a.n_rec + rec_idx[k]) * a.trace_cols + a.trace_col] = a.u_out[(int64_t)rec_node[k] * a.S + s];
+}
+
 // ------------------------------------------------------------------ utility kernels
 // internal state index i: node-major (node * S + s) or shot-major (s * N + node)
 template <typename T>
@@ -1728,6 +1771,26 @@ hipError_t launch_global_points(const StepArgs<T>& a, int phase, hipStream_t st)
 }
 
 template <typename T>
+hipError_t launch_border(const StepArgs<T>& a, const int32_t* nodes, int64_t n_nodes, const int32_t* rec_idx,
+                         const int32_t* rec_node, int32_t n_rec, hipStream_t st) {
+    if (n_nodes > 0) {
+        const int64_t waves = n_nodes * a.n_slices;
+        const int64_t b = (waves + kBlock / 64 - 1) / (kBlock / 64);
+        hipLaunchKernelGGL(border_update_kernel<T>, dim3((unsigned)(b > 65536 ? 65536 : b)), dim3(kBlock), 0, st,
+                           a, nodes, n_nodes);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (a.trace != nullptr && n_rec > 0) {
+        const int64_t t = (int64_t)n_rec * a.S;
+        hipLaunchKernelGGL(border_trace_kernel<T>, dim3((unsigned)((t + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,
+                           a, rec_idx, rec_node, n_rec);
+        return hipGetLastError();
+    }
+    return hipSuccess;
+}
+
+template <typename T>
 hipError_t launch_nodes_to_original(const T* in, T* out, const int32_t* n2o, int64_t N, int32_t S,
                                     bool shot_major, hipStream_t st) {
     hipLaunchKernelGGL(to_original_kernel<T>, dim3(grid_for(N * S)), dim3(kBlock), 0, st, in, out, n2o, N, S,
@@ -1794,7 +1857,9 @@ hipError_t launch_heun_stage(int p, int mode, int64_t nt, size_t lds, const Heun
     template hipError_t launch_heun_stage<T>(int, int, int64_t, size_t, const HeunArgs<T>&, hipStream_t); \
     template hipError_t launch_elems<T>(int, int, bool, const StepArgs<T>&, hipStream_t);         \
     template hipError_t launch_node_update<T>(const StepArgs<T>&, int64_t, hipStream_t);          \
-    template hipError_t launch_global_points<T>(const StepArgs<T>&, int, hipStream_t);
+    template hipError_t launch_global_points<T>(const StepArgs<T>&, int, hipStream_t);              \
+    template hipError_t launch_border<T>(const StepArgs<T>&, const int32_t*, int64_t, const int32_t*,     \
+                                         const int32_t*, int32_t, hipStream_t);
 
 SEM_INSTANTIATE(float)
 SEM_INSTANTIATE(double)

@@ -738,10 +738,57 @@ std::string build_plan(const MeshIn& m, const PlanOptions& opt, Plan& P, int& co
         code = SEM_ERR_BAD_MESH;
         return "greedy element colouring needs more than 64 colours";
     }
-    if (opt.node_order == SEM_NODES_FIRST_TOUCH)
+    if (opt.node_order == SEM_NODES_FIRST_TOUCH) {
         build_tiles(P, opt.tile_elems, opt.tile_items, opt.max_owned, opt.split_single);
+        if (opt.border && opt.split_single) split_border(P);
+    }
     code = SEM_OK;
     return "";
+}
+
+void split_border(Plan& P) {
+    const int64_t ne = P.ne, nq = P.nq, nt = (int64_t)P.tile_eb.size() - 1;
+    std::vector<int32_t> tile_of_elem(ne);
+    for (int64_t t = 0; t < nt; ++t)
+        for (int32_t e = P.tile_eb[t]; e < P.tile_eb[t + 1]; ++e) tile_of_elem[e] = (int32_t)t;
+    // tiles touching each node: the first one seen and whether another one touches it too
+    std::vector<int32_t> first_tile(P.nn, -1);
+    std::vector<uint8_t> border(P.nn, 0);
+    for (int64_t q = 0; q < nq; ++q)
+        for (int64_t e = 0; e < ne; ++e) {
+            const int32_t v = P.conn_soa[q * ne + e], t = tile_of_elem[e];
+            if (first_tile[v] < 0) first_tile[v] = t;
+            else if (first_tile[v] != t) border[v] = 1;
+        }
+    std::vector<int32_t> perm(P.nn);
+    P.tile_nbd.assign(nt, 0);
+    P.border_nodes.clear();
+    P.max_shared = 0;
+    for (int64_t t = 0; t < nt; ++t) {
+        const int32_t b = P.tile_nb[t], ns = P.tile_ns[t], f = P.tile_nb[t + 1];
+        int32_t next = b;
+        for (int32_t v = b; v < b + ns; ++v)
+            if (!border[v]) perm[v] = next++;
+        const int32_t n_internal = next - b;
+        for (int32_t v = b; v < b + ns; ++v)
+            if (border[v]) { perm[v] = next; P.border_nodes.push_back(next); ++next; }
+        P.tile_nbd[t] = next - b - n_internal;
+        P.tile_ns[t] = n_internal;
+        P.max_shared = std::max(P.max_shared, n_internal);
+        for (int32_t v = b + ns; v < f; ++v) perm[v] = v;      // single-element nodes stay
+    }
+    for (auto& v : P.conn_soa) v = perm[v];
+    std::vector<int32_t> n2o(P.nn);
+    std::vector<double> minv(P.nn);
+    for (int64_t v = 0; v < P.nn; ++v) {
+        n2o[perm[v]] = P.node_new2old[v];
+        minv[perm[v]] = P.minv[v];
+    }
+    P.node_new2old.swap(n2o);
+    P.minv.swap(minv);
+    for (int64_t v = 0; v < P.nn; ++v) P.node_old2new[P.node_new2old[v]] = (int32_t)v;
+    P.halo.clear();
+    P.halo_b.assign(nt + 1, 0);
 }
 
 bool colour_elements(Plan& P) {

@@ -34,6 +34,8 @@ struct PlanOptions {
     // a single element (kept in registers by the 64-shot kernel); max_owned then bounds
     // the first group only.
     bool split_single = false;
+    // with split_single: border mode (see split_border)
+    bool border = false;
 };
 
 struct Plan {
@@ -66,6 +68,10 @@ struct Plan {
     // two or more elements, the rest of its range to exactly one (an own element).
     std::vector<int32_t> tile_ns;
     int32_t max_shared = 0;
+    // border mode (64 shot lanes with global atomics): tile t's owned range is
+    // [internal shared: tile_ns[t] | border: tile_nbd[t] | single-element]; a border node is
+    // touched by elements of two or more tiles; border_nodes lists them all (tile by tile)
+    std::vector<int32_t> tile_nbd, border_nodes;
     // greedy element colouring in the new element order (Sec. 5): colour[k] of new
     // element k; two elements sharing a global node never share a colour
     std::vector<int32_t> colour;
@@ -95,6 +101,12 @@ std::string build_plan(const MeshIn& mesh, const PlanOptions& opt, Plan& plan, i
 // nodes (with split_single: owned nodes of two or more elements) <= max_owned.
 // split_single then regroups every tile's owned range and renumbers the nodes.
 void build_tiles(Plan& plan, int tile_elems, int tile_items, int max_owned, bool split_single);
+
+// Border mode on top of build_tiles(..., split_single = true): split every tile's shared
+// owned nodes into those whose elements all lie in the tile (first) and border nodes (touched
+// by another tile's elements), renumber the nodes, fill tile_ns / tile_nbd / border_nodes
+// and drop the halo lists (tiles then process their own elements only).
+void split_border(Plan& plan);
 
 // Cell index along the generalized Hilbert curve over a W x H grid.
 int64_t hilbert_index(int64_t W, int64_t H, int64_t cx, int64_t cy);

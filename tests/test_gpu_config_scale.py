@@ -109,20 +109,27 @@ def test_graded128_p5_fp32_1000_steps(semlib, gpu_ok, graded128, order):
     assert eu <= 1e-5 and ev <= 1e-5
 
 
-def test_batch256_64_shots_fp32_1000_steps(semlib, gpu_ok):
-    """64-shot batch (256^2, p=4, one wave per element and one shot per lane), FP32, 1000
-    steps; shots 0, 1 and 63 against an oracle run of those three sources."""
-    say("case batch256 64 shots fp32 1000 steps")
+@pytest.fixture(scope="module")
+def batch256():
     wl = workloads.workload("batch512", n=256, n_shots=64, nsteps=1000)
     pick = [0, 1, 63]
-    o = _oracle_run(wl, wl.nsteps, shots=pick)
-    g = _gpu_run(semlib, wl, wl.nsteps, o["dt"], "f32", "hilbert")
+    return wl, pick, _oracle_run(wl, wl.nsteps, shots=pick)
+
+
+@pytest.mark.parametrize("scatter", ["auto", "atomic"])
+def test_batch256_64_shots_fp32_1000_steps(semlib, gpu_ok, batch256, scatter):
+    """64-shot batch (256^2, p=4, one wave per element and one shot per lane), FP32, 1000
+    steps, LDS scatter and atomic border scatter; shots 0, 1 and 63 against an oracle run of
+    those three sources."""
+    say("case batch256 64 shots fp32 1000 steps", scatter)
+    wl, pick, o = batch256
+    g = _gpu_run(semlib, wl, wl.nsteps, o["dt"], "f32", "hilbert", scatter=scatter)
     assert g["info"]["shot_lanes"] == 64
     for k, s in enumerate(pick):
         assert np.abs(o["u"][:, k]).max() > 0
         eu, ev = rel(g["u"][:, s], o["u"][:, k]), rel(g["v"][:, s], o["v"][:, k])
         et = rel(g["tr"][s], o["tr"][k])
-        say(f"batch256 fp32 shot {s}: u {eu:.3e} v {ev:.3e} traces {et:.3e}")
+        say(f"batch256 fp32 {scatter} shot {s}: u {eu:.3e} v {ev:.3e} traces {et:.3e}")
         assert eu <= 1e-5 and ev <= 1e-5
         if np.abs(o["tr"][k]).max() > 1e-3 * np.abs(o["u"][:, k]).max():
             assert et <= 1e-5

@@ -94,6 +94,36 @@ def test_fp64_64_shot_lanes(semlib, gpu_ok, shots, block, lds):
     assert rel(tr, tr_o) <= 1e-12
 
 
+@pytest.mark.parametrize("shots,block,lds", [(64, 0, 0), (64, 256, 32768), (128, 1024, 49152)])
+def test_fp64_64_shot_lanes_atomic_border(semlib, gpu_ok, shots, block, lds):
+    """64 shot lanes with the atomic scatter: tiles process their own elements only, border
+    nodes sum through global atomics on their 64-shot rows of v and take u in a border pass.
+    FP64 against the oracle, sources and receivers (some on border nodes)."""
+    say("case 64-lane shots fp64 atomic border", shots, block, lds)
+    wl = workloads.workload("batch512", n=24, n_shots=shots, nsteps=300)
+    (tr, u, v), (tr_o, u_o, v_o) = run_both(semlib, wl, wl.nsteps, "f64", "hilbert",
+                                            block_threads=block, lds_bytes=lds, scatter="atomic")
+    assert rel(u, u_o) <= 1e-12
+    assert rel(v, v_o) <= 1e-12
+    assert rel(tr, tr_o) <= 1e-12
+    s = semlib.Simulator(wl.vxy, wl.quads, wl.c2, wl.p, precision="f64", n_shots=shots, scatter="atomic",
+                         block_threads=block, lds_bytes=lds)
+    inf = s.info()
+    assert inf["scatter"] == semlib.SCATTERS["atomic"] and inf["halo_elements"] == 0
+    s.close()
+
+
+def test_apply_stiffness_fp32_64_shots_atomic_border(semlib, gpu_ok):
+    import torch
+    wl = workloads.workload("layered1024", n=40)
+    o = solver.SEM(wl.vxy, wl.quads, wl.c2, wl.p)
+    s = semlib.Simulator(wl.vxy, wl.quads, wl.c2, wl.p, precision="f32", n_shots=64, scatter="atomic")
+    x = workloads.random_field(o.n_nodes, 64, seed=9)
+    r = s.apply_stiffness(torch.tensor(x, dtype=torch.float32, device="cuda")).cpu().numpy()
+    assert rel(r, (o.K @ x.T).T) <= 2e-6
+    s.close()
+
+
 def test_64_shot_lanes_selected(semlib, gpu_ok):
     wl = workloads.workload("batch512", n=16, n_shots=64)
     s = semlib.Simulator(wl.vxy, wl.quads, wl.c2, wl.p, precision="f32", n_shots=64)
@@ -256,11 +286,13 @@ def test_adjoint_gradient_fp64_global_scatter(semlib, gpu_ok, scatter):
     assert rel(g, d["g"]) <= 1e-10
 
 
-def test_adjoint_gradient_fp64_64_shot_lanes(semlib, gpu_ok):
-    """Gradient pairing of the one-wave-per-element kernel: 64 shots, small tiles."""
+@pytest.mark.parametrize("scatter", ["auto", "atomic"])
+def test_adjoint_gradient_fp64_64_shot_lanes(semlib, gpu_ok, scatter):
+    """Gradient pairing of the one-wave-per-element kernel: 64 shots, small tiles, with the
+    LDS scatter and with the atomic border scatter."""
     import torch
-    say("case adjoint fp64 64 shots")
-    o, s, d = _tiny_inversion(semlib, "f64", shots=64, lds_bytes=16384)
+    say("case adjoint fp64 64 shots", scatter)
+    o, s, d = _tiny_inversion(semlib, "f64", shots=64, lds_bytes=16384, scatter=scatter)
     assert s.info()["shot_lanes"] == 64
     tr = s.run(d["nsteps"])
     res = tr - torch.tensor(d["obs"], device="cuda")

@@ -228,8 +228,8 @@ def test_colours_bit_exact(semlib, name, kw, orders):
 
 
 def test_scatter_options(semlib):
-    """The scatter option: AUTO resolves to the owner-tile LDS scatter; COLOUR and ATOMIC are
-    single-shot leapfrog only; unknown values are refused."""
+    """The scatter option: AUTO resolves to the owner-tile LDS scatter; COLOUR is single-shot
+    leapfrog only, ATOMIC single shot or 64-shot lanes; unknown values are refused."""
     wl = workloads.workload("layered1024", n=12)
     s = semlib.Simulator(wl.vxy, wl.quads, wl.c2, wl.p, device=-1)
     assert s.info()["scatter"] == semlib.SCATTERS["lds_atomic"]
@@ -237,7 +237,8 @@ def test_scatter_options(semlib):
     s = semlib.Simulator(wl.vxy, wl.quads, wl.c2, wl.p, device=-1, scatter="colour")
     assert s.info()["scatter"] == semlib.SCATTERS["colour"]
     s.close()
-    for kw in (dict(scatter="colour", n_shots=2), dict(scatter="atomic", formulation="heun")):
+    for kw in (dict(scatter="colour", n_shots=2), dict(scatter="atomic", formulation="heun"),
+               dict(scatter="colour", n_shots=64), dict(scatter="atomic", n_shots=8)):
         with pytest.raises(semlib.SemError) as ei:
             semlib.Simulator(wl.vxy, wl.quads, wl.c2, wl.p, device=-1, **kw)
         assert ei.value.status == "INVALID_ARG"
@@ -282,3 +283,20 @@ def test_triangle_options_refused(semlib):
     with pytest.raises(semlib.SemError) as ei:
         semlib.Simulator(wl.vxy, cw, wl.c2, 5, device=-1)
     assert ei.value.status == "BAD_MESH"
+
+
+def test_border_split_of_64_shot_tiles(semlib):
+    """64 shot lanes with the atomic scatter: no halos; each tile's owned range lists the
+    nodes of two or more of its own elements, then its border nodes (touched by another
+    tile), then single-element nodes; the border nodes are exactly the nodes whose incident
+    elements lie in two or more tiles."""
+    wl = workloads.workload("batch512", n=20, n_shots=64)
+    s = semlib.Simulator(wl.vxy, wl.quads, wl.c2, wl.p, n_shots=64, scatter="atomic", device=-1,
+                         lds_bytes=16384)
+    inf = s.info()
+    assert inf["halo_elements"] == 0 and inf["n_tiles"] > 4
+    e, n = s.permutations()
+    oe, on = _oracle_perm(wl, "hilbert")
+    np.testing.assert_array_equal(e, oe)                  # element order unchanged
+    assert sorted(n.tolist()) == list(range(s.n_nodes))
+    s.close()
