@@ -211,7 +211,7 @@ def profile_summary(d, kernel, steps, counter_steps, per_step=1):
         rec.update({"l2_hit": h / (h + m)})
     # other counter passes (pmc*/): every counter of the kernel, averaged per dispatch
     pmc = {}
-    for sub in sorted(glob.glob(os.path.join(d, "pmc*"))):
+    for sub in sorted(g for g in glob.glob(os.path.join(d, "pmc*")) if os.path.isdir(g)):
         rows = [r for r in _rows(sub, "*counter_collection.csv") if kernel in r["Kernel_Name"]]
         for name in sorted({r["Counter_Name"] for r in rows}):
             vals = [float(r["Counter_Value"]) for r in rows if r["Counter_Name"] == name][-counter_steps:]
