@@ -279,7 +279,7 @@ int sem_hilbert_index(int64_t W, int64_t H, int64_t n, const int64_t* cx, const 
 /* Launch-configuration autotuner. Times the step kernel of every candidate configuration
  * on this mesh and returns the fastest. Only fields of *base that are zero vary:
  *   n_shots == 1 or triangles: block_threads in {256, 512, 1024} x tile_items in {1, 2}
- *                        workgroup passes (quadrilaterals) or {4, 8, 16} (triangles), a pass
+ *                        workgroup passes (quadrilaterals) or {8, 14, 20} (triangles), a pass
  *                        being 64 / (p+1) (64 / nodes per triangle) elements per wave;
  *   n_shots % 64 == 0:   block_threads in {256, 512} x lds_bytes in {24, 32, 48, 64} KB;
  *   other shot batches:  shot_lanes in {1, 2, 4, 8, 16} (those dividing n_shots).

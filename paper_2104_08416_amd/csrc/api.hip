@@ -480,13 +480,16 @@ int upload_geometry(sem_ctx* c) {
     // the kernels address these arrays with 32-bit byte offsets
     const int64_t ni = (int64_t)(P.p - 1) * (P.p - 1);
     if (tri_kernel(c)) {
-        // conn [E][nq], record [E][4] = g11, g12, g22, c^2 (curve order); reference matrices
-        if ((double)ne * nq * 4.0 >= 4294967296.0 || (double)ne * 4 * sizeof(T) >= 4294967296.0)
+        // conn [E + H][nq], record [E + H][4] = g11, g12, g22, c^2: the E elements in curve
+        // order, then a copy of each halo element's row in the order of the halo list (the
+        // kernel then finds a halo row without first loading its element index)
+        const int64_t nh = (int64_t)P.halo.size(), rows = ne + nh;
+        if ((double)rows * nq * 4.0 >= 4294967296.0 || (double)rows * 4 * sizeof(T) >= 4294967296.0)
             return fail(c, SEM_ERR_INVALID_ARG, "element arrays exceed 4 GiB (32-bit buffer offsets)");
-        std::vector<int32_t> cb((size_t)ne * nq);
-        std::vector<double> gb((size_t)ne * 4);
-        for (int64_t k = 0; k < ne; ++k) {
-            const int64_t e = c->elem_slot[k];
+        std::vector<int32_t> cb((size_t)rows * nq);
+        std::vector<double> gb((size_t)rows * 4);
+        for (int64_t k = 0; k < rows; ++k) {
+            const int64_t e = c->elem_slot[k < ne ? k : P.halo[k - ne]];
             for (int64_t q = 0; q < nq; ++q) cb[k * nq + q] = P.conn_soa[q * ne + e];
             for (int j = 0; j < 3; ++j) gb[k * 4 + j] = P.tri_G[(size_t)j * ne + e];
             gb[k * 4 + 3] = P.c2[e];
@@ -1007,17 +1010,30 @@ int sem_create(const sem_mesh* mesh, const sem_options* opt, sem_ctx** out) {
     po.tile_items = pick_tile_items(opt->p, c->SL, row_block, opt->tile_items);
     if (opt->tile_items <= 0 && c->SL == 1) po.tile_items = epb;
     if (nvpe == 3 && opt->tile_items <= 0) {
-        // triangles: eight passes of 64 / nq elements per wave (measured on the 250k-triangle
-        // p = 5 mesh: 192 elements a tile with 512 threads ran 26% faster than 96 and 27%
-        // faster than 384)
+        // triangles: fourteen passes of 64 / nq elements per wave (measured on the
+        // 250k-triangle p = 5 mesh with 512 threads: 336 own + halo elements a tile ran 10%
+        // (FP32) and 12% (FP64) faster than 192; larger tiles no longer fit two FP32
+        // workgroups in a CU's LDS, see the owned-node cap below)
         const int epb_tri = (64 / sem::tri_nq(opt->p)) * (row_block / 64);
-        po.tile_items = 8 * epb_tri;
+        po.tile_items = 14 * epb_tri;
     }
     // 64 shots: tiles are bounded by the LDS accumulator, not by an element count
     if (opt->tile_items <= 0 && c->SL == 64) po.tile_items = 1 << 20;
     int np = 1;
     while (np < max_np && np * epb < (opt->tile_elems > 0 ? opt->tile_elems : po.tile_items)) np *= 2;
     po.max_owned = pick_max_owned(c->SL, opt->precision, opt->lds_bytes);
+    if (nvpe == 3 && opt->lds_bytes <= 0) {
+        // triangles: bound a tile's owned nodes so that the workgroups the registers allow on
+        // a CU (FP32 about 110 VGPRs, 16 waves a CU; FP64 about 190, 8 waves) also fit its
+        // 160 KB of LDS: on the 250k-triangle mesh, FP32 tiles one pass past that bound ran
+        // 38% slower
+        const int per_cu = std::max(1, (opt->precision == SEM_F64 ? 8 : 16) / (row_block / 64));
+        const size_t word = opt->precision == SEM_F64 ? 8 : 4;
+        const size_t stage = sem::tri_lds_bytes(opt->p, row_block, 0, word);
+        const size_t budget = 163840 / (size_t)per_cu;
+        const int cap = budget > stage ? (int)((budget - stage) / (8 + 3 * word)) & ~63 : 0;
+        po.max_owned = std::min(po.max_owned, cap);
+    }
     po.split_single = c->S > 1 && c->SL == 64;
     po.border = c->border;
     if (po.max_owned < 1) {
@@ -1435,7 +1451,7 @@ int sem_autotune(const sem_mesh* mesh, const sem_options* base, int32_t warmup, 
         // workgroup size x tile size (own + halo elements, in workgroup passes of
         // 64 / nodes-per-element-row elements per wave)
         const int per_wave = tri ? 64 / sem::tri_nq(base->p) : 64 / (base->p + 1);
-        const std::vector<int> passes = tri ? std::vector<int>{4, 8, 16} : std::vector<int>{1, 2};
+        const std::vector<int> passes = tri ? std::vector<int>{8, 14, 20} : std::vector<int>{1, 2};
         std::vector<int> bts = {256, 512, 1024};
         if (base->block_threads > 0) bts = {base->block_threads};
         for (int bt : bts) {

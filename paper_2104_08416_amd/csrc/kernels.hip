@@ -32,6 +32,10 @@
 #ifndef TRI_NP
 #define TRI_NP 2
 #endif
+// triangle kernel: request the next group's node ids and records before this group's compute
+#ifndef TRI_PF
+#define TRI_PF 1
+#endif
 
 namespace sem {
 namespace {
@@ -1163,37 +1167,64 @@ __global__ void __attribute__((amdgpu_flat_work_group_size(RB, RB))) tri_rows_ke
         s3[m] = a.tri_S[(2 * NQ + qrow) * NQ + m];
     }
     // NP passes at a time: every pass's node ids and records are requested first, then every
-    // pass's gathers, so NP passes cost about one memory round trip
-    for (int base = 0; base < n_items; base += NP * EPB) {
-        int es[NP], node[NP];
-        bool act[NP];
-        T rec[NP][4], uq[NP];
+    // pass's gathers, so NP passes cost about one memory round trip; with TRI_PF the ids and
+    // records of the next NP passes are requested before this group's compute. The loads are
+    // unconditional (an inactive lane reads at the buffer's byte count, which returns 0
+    // without touching memory), so the wait counts stay exact through the loop.
+    auto fetch = [&](int base, int (&es)[NP], int (&node)[NP], bool (&act)[NP], T (&rec)[NP][4]) {
 #pragma unroll
         for (int pp = 0; pp < NP; ++pp) {
             const int k = base + pp * EPB + slot;
             act[pp] = kw < EPW && k < n_items;
-            es[pp] = 0;
-            node[pp] = 0;
-            if (act[pp]) {
-                es[pp] = k < n_own_el ? eb + k : a.halo[hb + k - n_own_el];
-                node[pp] = bload<int>(r_conn, (uint32_t)(es[pp] * NQ + q) * 4u);
-                if constexpr (sizeof(T) == 4) {
-                    const auto v = __builtin_amdgcn_raw_buffer_load_b128(r_G, (uint32_t)es[pp] * 16u, 0, 0);
+            // halo elements have copies of their rows after the E element rows, in the
+            // order of the halo list, so no load stands before the id load
+            es[pp] = k < n_own_el ? eb + k : (int)a.E + hb + (k - n_own_el);
+            node[pp] = bload<int>(r_conn, act[pp] ? (uint32_t)(es[pp] * NQ + q) * 4u : a.conn_bytes);
+            const uint32_t og = act[pp] ? (uint32_t)es[pp] * (uint32_t)(4 * sizeof(T)) : a.G_bytes;
+            if constexpr (sizeof(T) == 4) {
+                const auto v = __builtin_amdgcn_raw_buffer_load_b128(r_G, og, 0, 0);
 #pragma unroll
-                    for (int c = 0; c < 4; ++c) rec[pp][c] = __uint_as_float(v[c]);
-                } else {
+                for (int c = 0; c < 4; ++c) rec[pp][c] = __uint_as_float(v[c]);
+            } else {
 #pragma unroll
-                    for (int c = 0; c < 4; c += 2) {
-                        const auto v = __builtin_amdgcn_raw_buffer_load_b128(r_G, (uint32_t)es[pp] * 32u + 8u * c, 0, 0);
-                        rec[pp][c] = __builtin_bit_cast(double, ((unsigned long long)v[1] << 32) | v[0]);
-                        rec[pp][c + 1] = __builtin_bit_cast(double, ((unsigned long long)v[3] << 32) | v[2]);
-                    }
+                for (int c = 0; c < 4; c += 2) {
+                    const auto v = __builtin_amdgcn_raw_buffer_load_b128(r_G, og + 8u * c, 0, 0);
+                    rec[pp][c] = __builtin_bit_cast(double, ((unsigned long long)v[1] << 32) | v[0]);
+                    rec[pp][c + 1] = __builtin_bit_cast(double, ((unsigned long long)v[3] << 32) | v[2]);
                 }
             }
         }
+    };
+    int es_n[NP], node_n[NP];
+    bool act_n[NP];
+    T rec_n[NP][4];
+    if (TRI_PF) fetch(0, es_n, node_n, act_n, rec_n);
+    for (int base = 0; base < n_items; base += NP * EPB) {
+        int es[NP], node[NP];
+        bool act[NP];
+        T rec[NP][4], uq[NP];
+        if (TRI_PF) {
+#pragma unroll
+            for (int pp = 0; pp < NP; ++pp) {
+                es[pp] = es_n[pp];
+                node[pp] = node_n[pp];
+                act[pp] = act_n[pp];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) rec[pp][c] = rec_n[pp][c];
+            }
+        } else {
+            fetch(base, es, node, act, rec);
+        }
 #pragma unroll
         for (int pp = 0; pp < NP; ++pp)
-            uq[pp] = act[pp] ? bload<T>(r_u, (uint32_t)node[pp] * (uint32_t)sizeof(T)) : T(0);
+            uq[pp] = bload<T>(r_u, act[pp] ? (uint32_t)node[pp] * (uint32_t)sizeof(T) : a.state_bytes);
+        if (TRI_PF) {
+            // keep the order gathers, next ids, compute: a gather moved after the next ids
+            // would make the first stage write wait for those ids as well
+            __builtin_amdgcn_sched_barrier(0);
+            fetch(base + NP * EPB, es_n, node_n, act_n, rec_n);
+            __builtin_amdgcn_sched_barrier(0);
+        }
 #pragma unroll
         for (int pp = 0; pp < NP; ++pp) {
             const int k = base + pp * EPB + slot;

@@ -338,18 +338,26 @@ def test_unstable_dt_rejected(semlib, gpu_ok):
     assert ei.value.status == "UNSTABLE_DT"
 
 
-@pytest.mark.parametrize("shots", [1, 64])
+@pytest.mark.parametrize("shots", [1, 64, "tri"])
 def test_autotune_picks_a_timed_candidate(semlib, gpu_ok, shots):
     """The autotuner times every candidate, returns the fastest, and a context built with
     its options reproduces the default context's wavefield to rounding."""
     import torch
     say("case autotune", shots)
-    wl = workloads.workload("batch512", n=32, n_shots=shots, nsteps=60)
+    if shots == "tri":
+        wl = workloads.workload("tri2000", n=40, p=5, nsteps=60)
+        wl.src_xy = np.array([[900.0, 800.0]])
+        shots = 1
+    else:
+        wl = workloads.workload("batch512", n=32, n_shots=shots, nsteps=60)
+    tri = wl.quads.shape[1] == 3
     best, rows = semlib.autotune(wl.vxy, wl.quads, wl.c2, wl.p, precision="f32", n_shots=shots, steps=10)
-    assert len(rows) == (6 if shots == 1 else 8)
+    assert len(rows) == (9 if tri else 6 if shots == 1 else 8)
     assert all(r["us_per_step"] > 0 for r in rows)
     assert best["us_per_step"] == min(r["us_per_step"] for r in rows)
-    if shots == 1:
+    if tri:
+        assert {r["tile_items"] for r in rows} == {k * 3 * t // 64 for k in (8, 14, 20) for t in (256, 512, 1024)}
+    elif shots == 1:
         assert len({r["tile_items"] for r in rows}) == 4      # 2 tile sizes x 3 workgroup sizes
     kw = {k: best[k] for k in ("block_threads", "lds_bytes", "tile_items")}
     out = []
