@@ -644,6 +644,17 @@ __global__ void __launch_bounds__(BT) step_shots_kernel(const StepArgs<T> a) {
 // moving LDS accesses across it, and the lanes of one wave execute LDS instructions in order.
 __device__ __forceinline__ void wave_sync() { __builtin_amdgcn_wave_barrier(); }
 
+// Workgroup barrier that orders LDS only. __syncthreads() also waits for every global
+// load the wave has in flight, which would hold each wave at the block's first barrier
+// until the direct-to-LDS prefetch of the update operands had landed; those loads are
+// waited for after the element loop instead.
+__device__ __forceinline__ void lds_barrier() {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0xC07F);                // lgkmcnt(0): this wave's LDS writes done
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
 // Row j of D, column j of D, xi_j and w_j in registers, selected from the uniform kernel
 // arguments (no per-lane memory reads).
 template <typename T, int P, typename Args>
@@ -793,7 +804,7 @@ step_rows_kernel(const StepArgs<T> a) {
         lds_prefetch<RB>(make_rsrc(a.dtminv, a.state_bytes), off, pre_m, ndw);
     }
     for (int i = threadIdx.x; i < nown; i += kRowBlock) acc[i] = 0.0;
-    __syncthreads();
+    lds_barrier();
 
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int kw = lane / N;                           // element slot inside the wave
@@ -1148,7 +1159,7 @@ __global__ void __attribute__((amdgpu_flat_work_group_size(RB, RB))) tri_rows_ke
         lds_prefetch<RB>(make_rsrc(a.dtminv, a.state_bytes), off, pre_m, ndw);
     }
     for (int i = threadIdx.x; i < nown; i += RB) acc[i] = 0.0;
-    __syncthreads();
+    lds_barrier();
 
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int kw = lane / NQ, q = lane - kw * NQ;
@@ -1481,15 +1492,29 @@ __global__ void __launch_bounds__(kRowBlock / 2) heun_rows_kernel(const HeunArgs
         acc[i] = 0.0;
         if constexpr (FUSE) acc2[i] = 0.0;
     }
-    __syncthreads();
+    lds_barrier();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int kw = lane / N, j = lane - kw * N;
     const int slot = wave * EPW + kw;
     T* st = stage + slot * NQP;
-    T xij = a.xi[0], wj = a.w[0];
+    // FP32: row j and column j of D in registers, selected from the uniform kernel arguments
+    // (indexing the arguments by the lane's row reloads them from memory for every element:
+    // 9% of the FP32 step; in FP64 the ten extra registers cost 2%, so it reloads them)
+    constexpr bool HOIST = sizeof(T) == 4;
+    T Dj[N], DjT[N], xij = a.xi[0], wj = a.w[0];
+#pragma unroll
+    for (int m = 0; m < N; ++m) {
+        Dj[m] = a.D[m];
+        DjT[m] = a.D[m * N];
+    }
 #pragma unroll
     for (int jj = 1; jj < N; ++jj)
         if (j == jj) {
+#pragma unroll
+            for (int m = 0; m < N; ++m) {
+                Dj[m] = a.D[jj * N + m];
+                DjT[m] = a.D[m * N + jj];
+            }
             xij = a.xi[jj];
             wj = a.w[jj];
         }
@@ -1534,7 +1559,7 @@ __global__ void __launch_bounds__(kRowBlock / 2) heun_rows_kernel(const HeunArgs
             wave_sync();
 #pragma unroll
             for (int m = 0; m < N; ++m) {
-                const T dmj = a.D[m * N + j];
+                const T dmj = HOIST ? DjT[m] : a.D[m * N + j];
 #pragma unroll
                 for (int aa = 0; aa < N; ++aa) r[aa] -= dmj * st[aa + N * m];
             }
@@ -1557,7 +1582,7 @@ __global__ void __launch_bounds__(kRowBlock / 2) heun_rows_kernel(const HeunArgs
 #pragma unroll
                 for (int m = 0; m < N; ++m) {
                     gxi += a.D[i * N + m] * u[m];
-                    geta += a.D[j * N + m] * st[i + N * m];
+                    geta += (HOIST ? Dj[m] : a.D[j * N + m]) * st[i + N * m];
                 }
                 const T inv = T(1) / (xs * yt - xt * ys);
                 dx = (yt * gxi - ys * geta) * inv;
