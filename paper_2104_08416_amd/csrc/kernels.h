@@ -33,8 +33,8 @@ struct StepArgs {
     // tiling
     const int32_t* tile_eb;   // [T+1] element range of each tile
     const int32_t* tile_nb;   // [T+1] owned node range of each tile
-    const int32_t* tile_ns;   // [T] 64-shot kernel: owned nodes of two or more elements
-                              //     (the first tile_ns[t] of the range; the rest have one)
+    const int32_t* tile_ns;   // [T] 64-shot kernel: owned nodes on an element edge (the first
+                              //     tile_ns[t] of the range; the rest are element-interior)
     const int32_t* tile_nbd;  // [T] 64-shot atomic scatter: owned border nodes, right after
                               //     the tile_ns[t] internal ones (null otherwise)
     const int32_t* halo_b;    // [T+1]

@@ -354,8 +354,18 @@ __device__ __forceinline__ double rlane<double>(double v, int l) {
 // elements) receives -dt/M c^2 (K_e u_e) from every element through global FP atomics on its
 // 64-shot row of v (r_out in modes 1, 2), and border_update_kernel forms its u_out after the
 // launch. No halo element is recomputed and no halo row gathered.
-template <typename T, int P, int BT, bool BORDER>
-__global__ void __launch_bounds__(BT) step_shots_kernel(const StepArgs<T> a) {
+//
+// GRAD: the adjoint step, which also pairs each element's K_e u with u_pair (in FP32 a
+// separate instantiation, so the forward loop holds no loads that only the adjoint needs;
+// FP64 runs this one for both, the pairing skipped when grad is null: without that branch
+// its forward step took 218 VGPRs, two waves per SIMD instead of three).
+// FP32 defers each element's interior-node stores until the next element's loads are issued:
+// a wave's loads and stores complete in issue order, so stores issued before a load would be
+// waited for together with it.
+template <typename T, int P, int BT, bool BORDER, bool GRAD>
+__global__ void __launch_bounds__(BT)
+    __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && P <= 4 ? 4 : 1, 8)))
+    step_shots_kernel(const StepArgs<T> a) {
     constexpr int N = P + 1, NQ = N * N, SL = 64, NW = BT / 64;
     constexpr int NI = (P - 1) * (P - 1);              // element-interior nodes
     constexpr int REC = 3 * NQ + 1 + NI;               // g11[nq] g12[nq] g22[nq] c2 dt/M[ni]
@@ -372,8 +382,8 @@ __global__ void __launch_bounds__(BT) step_shots_kernel(const StepArgs<T> a) {
     const int s0 = (logical - tile * a.n_slices) * SL;
     const int nb = a.tile_nb[tile];
     const int nown = a.tile_nb[tile + 1] - nb;
-    const int ns = a.tile_ns[tile];                     // owned nodes of >= 2 elements (BORDER:
-                                                        // of >= 2 elements all in this tile)
+    const int ns = a.tile_ns[tile];                     // owned nodes on an element edge (BORDER:
+                                                        // whose elements all lie in this tile)
     const int nbd = BORDER ? a.tile_nbd[tile] : 0;     // BORDER: owned border nodes, after those
     const int eb = a.tile_eb[tile];
     const int n_own_el = a.tile_eb[tile + 1] - eb;
@@ -405,20 +415,45 @@ __global__ void __launch_bounds__(BT) step_shots_kernel(const StepArgs<T> a) {
     auto elem_of = [&](int k) { return k < n_own_el ? eb + k : halo[hb + k - n_own_el]; };
     // An element's node ids (lane q holds id q) and its record (word i in lane i % 64 of
     // register i / 64) are read one element ahead, into VGPRs, and broadcast with readlane.
-    auto load_ids = [&](int e) {
-        return bload<int>(r_conn, (uint32_t)(e * NQ + (lane < NQ ? lane : 0)) * 4u);
+    // The loads in the element loop are unconditional (past the last element, or where a value
+    // is not needed, a lane reads at the buffer's byte count, which returns 0), so the waits
+    // count exactly what they need.
+    auto load_ids = [&](bool act, int e) {
+        return bload<int>(r_conn, act ? (uint32_t)(e * NQ + (lane < NQ ? lane : 0)) * 4u : a.conn_bytes);
     };
-    auto load_rec = [&](int e, T* gv) {
+    auto load_rec = [&](bool act, int e, T* gv) {
 #pragma unroll
         for (int rg = 0; rg < NREG; ++rg) {
             const int w = rg * 64 + lane;
-            gv[rg] = bload<T>(r_G, (uint32_t)(e * REC + (w < REC ? w : 0)) * (uint32_t)sizeof(T));
+            gv[rg] = bload<T>(r_G, act ? (uint32_t)(e * REC + (w < REC ? w : 0)) * (uint32_t)sizeof(T) : a.G_bytes);
         }
     };
-    int e_next = wave < n_items ? elem_of(wave) : 0;
-    int cv_next = load_ids(e_next);
+    constexpr bool DEFER = sizeof(T) == 4;
+    constexpr int ND = DEFER && NI > 0 ? NI : 1;
+    // the element-interior results of the previous element (mode 0: v and u_out; modes 1, 2:
+    // r_out) and that element's ids; st_d: whether it is an own element
+    T dv0[ND], dv1[ND];
+    int cv_d = 0;
+    bool st_d = false;
+    const bool mode0 = a.mode == 0;
+    const rsrc_t r_s0 = mode0 ? r_v : r_ro, r_s1 = mode0 ? r_uo : r_ro;
+    auto flush = [&]() {
+#pragma unroll
+        for (int b = 1; b < P; ++b)
+#pragma unroll
+            for (int c = 1; c < P; ++c) {
+                const int ii = (b - 1) * (P - 1) + c - 1;
+                const uint32_t off = st_d ? (uint32_t)__builtin_amdgcn_readlane(cv_d, c + N * b) * ustride + soff
+                                          : a.state_bytes;
+                bstore(r_s0, off, dv0[ii]);
+                bstore(r_s1, mode0 ? off : a.state_bytes, dv1[ii]);
+            }
+    };
+    const bool act0 = wave < n_items;
+    int e_next = act0 ? elem_of(wave) : 0;
+    int cv_next = load_ids(act0, e_next);
     T gv_next[NREG];
-    load_rec(e_next, gv_next);
+    load_rec(act0, e_next, gv_next);
     for (int k = wave; k < n_items; k += NW) {
         const bool own = k < n_own_el;
         const int e = e_next;
@@ -432,20 +467,26 @@ __global__ void __launch_bounds__(BT) step_shots_kernel(const StepArgs<T> a) {
             u[q] = bload<T>(r_u, (uint32_t)__builtin_amdgcn_readlane(cv, q) * ustride + soff);
         // v at the element-interior nodes (nodes of this element alone, finished below):
         // requested now so that the loads overlap the contraction
+        const bool upd = own && mode0;
         T vin[NI > 0 ? NI : 1];
-        if (own && a.mode == 0) {
+        // FP64 (no deferred stores) keeps these loads in branches: unconditional, they raised
+        // its registers from 166 to 218 (three waves per SIMD to two)
+        if (DEFER || upd) {
 #pragma unroll
             for (int b = 1; b < P; ++b)
 #pragma unroll
                 for (int c = 1; c < P; ++c)
                     vin[(b - 1) * (P - 1) + c - 1] =
-                        bload<T>(r_v, (uint32_t)__builtin_amdgcn_readlane(cv, c + N * b) * ustride + soff);
+                        bload<T>(r_v, upd ? (uint32_t)__builtin_amdgcn_readlane(cv, c + N * b) * ustride + soff
+                                          : a.state_bytes);
         }
-        if (k + NW < n_items) {
-            e_next = elem_of(k + NW);
-            cv_next = load_ids(e_next);
-            load_rec(e_next, gv_next);
+        const bool act_n = k + NW < n_items;
+        if (DEFER || act_n) {
+            e_next = act_n ? elem_of(k + NW) : 0;
+            cv_next = load_ids(act_n, e_next);
+            load_rec(act_n, e_next, gv_next);
         }
+        if constexpr (DEFER) flush();
         // word w of the record
         auto rec = [&](int w) { return rlane(gv[w / 64], w % 64); };
         T r[NQ];
@@ -481,16 +522,19 @@ __global__ void __launch_bounds__(BT) step_shots_kernel(const StepArgs<T> a) {
             }
         }
         const T c2 = rec(3 * NQ);
-        if (a.grad != nullptr && own) {
-            T dot = T(0);
+        if constexpr (GRAD) {
+            if (a.grad != nullptr && own) {
+                T dot = T(0);
 #pragma unroll
-            for (int q = 0; q < NQ; ++q)
-                dot += r[q] * bload<T>(r_pair, (uint32_t)__builtin_amdgcn_readlane(cv, q) * ustride + soff);
-            dot = group_sum<64>(dot);
-            if (lane == 0) atomicAdd(&a.grad[e], (double)dot);
+                for (int q = 0; q < NQ; ++q)
+                    dot += r[q] * bload<T>(r_pair, (uint32_t)__builtin_amdgcn_readlane(cv, q) * ustride + soff);
+                dot = group_sum<64>(dot);
+                if (lane == 0) atomicAdd(&a.grad[e], (double)dot);
+            }
         }
-        // Node ids are wave-uniform, so these branches do not diverge. Nodes of several
-        // elements accumulate in LDS; a node of this element alone is finished here.
+        // Node ids are wave-uniform, so these branches do not diverge. Every owned node on an
+        // element edge accumulates in LDS (BORDER: unless another tile's elements touch it);
+        // an edge node owned by another tile is that tile's (a halo element's contribution).
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
             const int qa = q % N, qb = q / N;
@@ -503,47 +547,40 @@ __global__ void __launch_bounds__(BT) step_shots_kernel(const StepArgs<T> a) {
                 // a border node, this tile's or another's: its sum completes after every tile
                 const T rt = c2 * r[q];
                 const int64_t g = (int64_t)node * S + s0 + lane;
-                if (a.mode == 0) atomicAdd(&a.v[g], -(dtminv[node] * rt));
+                if (mode0) atomicAdd(&a.v[g], -(dtminv[node] * rt));
                 else atomicAdd(&a.r_out[g], a.mode == 2 ? dtminv[node] * rt : rt);
-            } else if (own && (unsigned)loc < (unsigned)nown) {
-                // a node on the domain boundary that only this element touches
-                const T rt = c2 * r[q];
-                const uint32_t off = (uint32_t)node * ustride + soff;
-                if (a.mode == 0) {
-                    const T vn = bload<T>(r_v, off) - dtminv[node] * rt;
-                    bstore(r_v, off, vn);
-                    bstore(r_uo, off, u[q] + a.dt * vn);
-                } else {
-                    bstore(r_ro, off, a.mode == 2 ? dtminv[node] * rt : rt);
-                }
             }
         }
         // element-interior nodes: single-element, owned by this element's tile
-        if (own) {
-            if (a.mode == 0) {
 #pragma unroll
-                for (int b = 1; b < P; ++b)
+        for (int b = 1; b < P; ++b)
 #pragma unroll
-                    for (int c = 1; c < P; ++c) {
-                        const int q = c + N * b, ii = (b - 1) * (P - 1) + c - 1;
-                        const uint32_t off = (uint32_t)__builtin_amdgcn_readlane(cv, q) * ustride + soff;
-                        const T vn = vin[ii] - rec(3 * NQ + 1 + ii) * (c2 * r[q]);
+            for (int c = 1; c < P; ++c) {
+                const int q = c + N * b, ii = (b - 1) * (P - 1) + c - 1;
+                if constexpr (DEFER) {
+                    const T rt = c2 * r[q];
+                    const T dm = rec(3 * NQ + 1 + ii);
+                    dv0[ii] = mode0 ? vin[ii] - dm * rt : (a.mode == 2 ? dm * rt : rt);
+                    dv1[ii] = u[q] + a.dt * dv0[ii];
+                } else if (own) {
+                    const T rt = c2 * r[q];
+                    const T dm = rec(3 * NQ + 1 + ii);
+                    const uint32_t off = (uint32_t)__builtin_amdgcn_readlane(cv, q) * ustride + soff;
+                    if (mode0) {
+                        const T vn = vin[ii] - dm * rt;
                         bstore(r_v, off, vn);
                         bstore(r_uo, off, u[q] + a.dt * vn);
+                    } else {
+                        bstore(r_ro, off, a.mode == 2 ? dm * rt : rt);
                     }
-            } else {
-#pragma unroll
-                for (int b = 1; b < P; ++b)
-#pragma unroll
-                    for (int c = 1; c < P; ++c) {
-                        const int q = c + N * b, ii = (b - 1) * (P - 1) + c - 1;
-                        const uint32_t off = (uint32_t)__builtin_amdgcn_readlane(cv, q) * ustride + soff;
-                        const T rt = c2 * r[q];
-                        bstore(r_ro, off, a.mode == 2 ? rec(3 * NQ + 1 + ii) * rt : rt);
-                    }
+                }
             }
+        if constexpr (DEFER) {
+            cv_d = cv;
+            st_d = own;
         }
     }
+    if constexpr (DEFER) flush();
     __syncthreads();
 
     // Sources and adjoint injection: force f enters as acc -= f at accumulated nodes; at
@@ -1380,7 +1417,16 @@ hipError_t launch_rows(int64_t n_tiles, size_t lds, const StepArgs<T>& a, hipStr
 
 template <typename T, int P, int BT>
 hipError_t launch_shots(int64_t n_tiles, size_t lds, const StepArgs<T>& a, hipStream_t st) {
-    auto fn = a.tile_nbd != nullptr ? step_shots_kernel<T, P, BT, true> : step_shots_kernel<T, P, BT, false>;
+    // FP32 forward steps run the instantiation without the pairing (113 VGPRs, four waves
+    // per SIMD); the one with it has 89 VGPRs and five waves but ran 2.5% slower
+    void (*fn)(const StepArgs<T>);
+    if constexpr (sizeof(T) == 8) {
+        fn = a.tile_nbd != nullptr ? step_shots_kernel<T, P, BT, true, true> : step_shots_kernel<T, P, BT, false, true>;
+    } else {
+        fn = a.tile_nbd != nullptr
+                 ? (a.grad != nullptr ? step_shots_kernel<T, P, BT, true, true> : step_shots_kernel<T, P, BT, true, false>)
+                 : (a.grad != nullptr ? step_shots_kernel<T, P, BT, false, true> : step_shots_kernel<T, P, BT, false, false>);
+    }
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

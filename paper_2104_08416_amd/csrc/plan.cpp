@@ -375,10 +375,19 @@ void build_tiles(Plan& P, int tile_elems, int tile_items, int max_owned, bool sp
             for (int64_t e = 0; e < ne; ++e) n2e[fill[P.conn_soa[q * ne + e]]++] = (int32_t)e;
     }
     auto node_of = [&](int64_t e, int64_t q) { return P.conn_soa[q * ne + e]; };
+    // accum[v]: the node takes an accumulator slot. With split_single only the nodes on an
+    // element's edge do (those of two or more elements and those on the domain boundary);
+    // the element-interior nodes of a quadrilateral are finished by their element alone.
+    std::vector<uint8_t> accum(P.nn, split_single ? 0 : 1);
+    if (split_single)
+        for (int64_t q = 0; q < nq; ++q) {
+            const int64_t a = q % P.n, b = q / P.n;
+            if (a == 0 || a == P.p || b == 0 || b == P.p)
+                for (int64_t e2 = 0; e2 < ne; ++e2) accum[node_of(e2, q)] = 1;
+        }
     // counted[v] = number of nodes below v that occupy an accumulator slot
     std::vector<int64_t> counted(P.nn + 1, 0);
-    for (int64_t v = 0; v < P.nn; ++v)
-        counted[v + 1] = counted[v] + ((!split_single || n2e_b[v + 1] - n2e_b[v] > 1) ? 1 : 0);
+    for (int64_t v = 0; v < P.nn; ++v) counted[v + 1] = counted[v] + accum[v];
     P.tile_elems = tile_elems > 0 ? tile_elems : 0;
     P.tile_items = tile_elems > 0 ? 0 : tile_items;
     P.tile_eb.assign(1, 0);
@@ -440,7 +449,7 @@ void build_tiles(Plan& P, int tile_elems, int tile_items, int max_owned, bool sp
     P.tile_ns.clear();
     P.max_shared = P.max_owned;
     if (!split_single) return;
-    // stable partition of every owned range: shared nodes, then single-element nodes
+    // stable partition of every owned range: edge nodes, then element-interior nodes
     const int64_t nt = (int64_t)P.tile_nb.size() - 1;
     std::vector<int32_t> perm(P.nn);
     P.tile_ns.resize(nt);
@@ -449,11 +458,11 @@ void build_tiles(Plan& P, int tile_elems, int tile_items, int max_owned, bool sp
         const int32_t b = P.tile_nb[k], f = P.tile_nb[k + 1];
         int32_t next = b;
         for (int32_t v = b; v < f; ++v)
-            if (n2e_b[v + 1] - n2e_b[v] > 1) perm[v] = next++;
+            if (accum[v]) perm[v] = next++;
         P.tile_ns[k] = next - b;
         P.max_shared = std::max<int32_t>(P.max_shared, next - b);
         for (int32_t v = b; v < f; ++v)
-            if (n2e_b[v + 1] - n2e_b[v] <= 1) perm[v] = next++;
+            if (!accum[v]) perm[v] = next++;
     }
     for (auto& v : P.conn_soa) v = perm[v];
     std::vector<int32_t> n2o(P.nn);
@@ -775,7 +784,7 @@ void split_border(Plan& P) {
         P.tile_nbd[t] = next - b - n_internal;
         P.tile_ns[t] = n_internal;
         P.max_shared = std::max(P.max_shared, n_internal);
-        for (int32_t v = b + ns; v < f; ++v) perm[v] = v;      // single-element nodes stay
+        for (int32_t v = b + ns; v < f; ++v) perm[v] = v;      // element-interior nodes stay
     }
     for (auto& v : P.conn_soa) v = perm[v];
     std::vector<int32_t> n2o(P.nn);

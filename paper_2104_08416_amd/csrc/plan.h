@@ -64,12 +64,13 @@ struct Plan {
     int tile_items = 0;                      // adaptive cap on own + halo elements
     std::vector<int32_t> tile_eb, tile_nb, halo_b, halo;
     int32_t max_owned = 0;
-    // split_single: tile t's owned nodes [tile_nb[t], tile_nb[t] + tile_ns[t]) belong to
-    // two or more elements, the rest of its range to exactly one (an own element).
+    // split_single: tile t's owned nodes [tile_nb[t], tile_nb[t] + tile_ns[t]) lie on an
+    // element edge (nodes of two or more elements, or on the domain boundary); the rest of its
+    // range are element-interior nodes of its own elements.
     std::vector<int32_t> tile_ns;
     int32_t max_shared = 0;
     // border mode (64 shot lanes with global atomics): tile t's owned range is
-    // [internal shared: tile_ns[t] | border: tile_nbd[t] | single-element]; a border node is
+    // [internal edge: tile_ns[t] | border: tile_nbd[t] | element-interior]; a border node is
     // touched by elements of two or more tiles; border_nodes lists them all (tile by tile)
     std::vector<int32_t> tile_nbd, border_nodes;
     // greedy element colouring in the new element order (Sec. 5): colour[k] of new
@@ -98,12 +99,12 @@ std::string build_plan(const MeshIn& mesh, const PlanOptions& opt, Plan& plan, i
 
 // (Re)build the tiling: fixed tiles of `tile_elems` elements when > 0, else adaptive tiles
 // that grow along the element order while own + halo elements <= tile_items and owned
-// nodes (with split_single: owned nodes of two or more elements) <= max_owned.
+// nodes (with split_single: owned nodes on an element edge) <= max_owned.
 // split_single then regroups every tile's owned range and renumbers the nodes.
 void build_tiles(Plan& plan, int tile_elems, int tile_items, int max_owned, bool split_single);
 
-// Border mode on top of build_tiles(..., split_single = true): split every tile's shared
-// owned nodes into those whose elements all lie in the tile (first) and border nodes (touched
+// Border mode on top of build_tiles(..., split_single = true): split every tile's edge
+// nodes into those whose elements all lie in the tile (first) and border nodes (touched
 // by another tile's elements), renumber the nodes, fill tile_ns / tile_nbd / border_nodes
 // and drop the halo lists (tiles then process their own elements only).
 void split_border(Plan& plan);

@@ -50,13 +50,19 @@ def test_permutations_bit_exact(semlib, name, kw, orders):
 
 @pytest.mark.parametrize("name,kw", [("batch512", dict(n=48)), ("graded1414", dict(n=30, p=5))])
 def test_64_shot_lanes_regroup_owned_nodes(semlib, name, kw):
-    """With 64 shot lanes every tile's owned range lists its nodes of two or more elements
-    first, then its nodes of one element, each group in first-touch order; the element
-    order is unchanged and the accumulator slots fit the LDS budget."""
+    """With 64 shot lanes every tile's owned range lists its nodes on an element edge first
+    (nodes of two or more elements and nodes on the domain boundary), then its
+    element-interior nodes, each group in first-touch order; the element order is unchanged
+    and the accumulator slots fit the LDS budget."""
     wl = workloads.workload(name, **kw)
     conn, n_nodes = mesh.global_numbering(wl.quads, wl.vxy.shape[0], wl.p)
     start, _, _ = solver.node_incidence(conn, n_nodes)
-    mult = np.diff(start)
+    n = wl.p + 1
+    a_loc, b_loc = np.arange(n * n) % n, np.arange(n * n) // n
+    edge_q = (a_loc == 0) | (a_loc == wl.p) | (b_loc == 0) | (b_loc == wl.p)
+    edge = np.zeros(n_nodes, bool)
+    edge[conn[:, edge_q].ravel()] = True
+    assert edge[np.diff(start) > 1].all()           # every shared node lies on an edge
     oe, on = _oracle_perm(wl, "hilbert")
     s = semlib.Simulator(wl.vxy, wl.quads, wl.c2, wl.p, device=-1, n_shots=64, lds_bytes=16384)
     inf = s.info()
@@ -74,7 +80,7 @@ def test_64_shot_lanes_regroup_owned_nodes(semlib, name, kw):
     b = 0
     for t in ends:
         blk = n[b:t]
-        shared = mult[blk] > 1
+        shared = edge[blk]
         k = int(shared.sum())
         assert shared[:k].all() and not shared[k:].any()
         assert np.all(np.diff(pos[blk[:k]]) > 0) and np.all(np.diff(pos[blk[k:]]) > 0)
