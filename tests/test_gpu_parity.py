@@ -286,6 +286,28 @@ def test_adjoint_gradient_fp64_global_scatter(semlib, gpu_ok, scatter):
     assert rel(g, d["g"]) <= 1e-10
 
 
+def test_colour_scatter_is_bitwise_reproducible(semlib, gpu_ok):
+    """The paper's colour passes add each node's contributions one colour class after another,
+    at most one per class, so a rerun (and the adjoint's recomputation of the forward from its
+    checkpoints) reproduces every bit: FP64, 80 steps, traces, wavefield and the gradient
+    equal to the last bit on a second run."""
+    import torch
+    say("case colour bitwise")
+    o, s, d = _tiny_inversion(semlib, "f64", shots=1, scatter="colour")
+    runs = []
+    for _ in range(2):
+        s.reset()
+        tr = s.run(d["nsteps"])
+        u = s.get_field(semlib.FIELD_U).cpu().numpy()
+        res = (tr - torch.tensor(d["obs"], device="cuda")).contiguous()
+        g = s.adjoint_gradient(res, d["nsteps"], 30).cpu().numpy()
+        runs.append((tr.cpu().numpy(), u, g))
+    s.close()
+    for a, b in zip(runs[0], runs[1]):
+        assert np.array_equal(a.view(np.uint64), b.view(np.uint64))
+    assert rel(runs[0][2], d["g"]) <= 1e-10
+
+
 @pytest.mark.parametrize("scatter", ["auto", "atomic"])
 def test_adjoint_gradient_fp64_64_shot_lanes(semlib, gpu_ok, scatter):
     """Gradient pairing of the one-wave-per-element kernel: 64 shots, small tiles, with the
