@@ -650,8 +650,10 @@ int set_sources_t(sem_ctx* c, int32_t n, const double* xy, const int32_t* shot, 
     const int64_t nt = (int64_t)P.tile_eb.size() - 1;
     struct Ent { int64_t tile; int32_t loc; int32_t shot; double w; };
     std::vector<Ent> ents;
+    std::vector<int32_t> near((size_t)std::max(n, 0));
+    sem::nearest_nodes(P, n, xy, near.data());
     for (int32_t i = 0; i < n; ++i) {
-        const int32_t old = sem::nearest_node(P, xy[2 * i], xy[2 * i + 1]);
+        const int32_t old = near[i];
         if (node_out) node_out[i] = old;
         const int32_t nw = P.node_old2new[old];
         const int64_t t = tile_of_node(P, nw);
@@ -696,8 +698,10 @@ int set_receivers_t(sem_ctx* c, int32_t n, const double* xy, int32_t* node_out) 
     const int64_t nt = (int64_t)P.tile_eb.size() - 1;
     struct Ent { int64_t tile; int32_t loc; int32_t r; };
     std::vector<Ent> ents;
+    std::vector<int32_t> near((size_t)std::max(n, 0));
+    sem::nearest_nodes(P, n, xy, near.data());
     for (int32_t i = 0; i < n; ++i) {
-        const int32_t old = sem::nearest_node(P, xy[2 * i], xy[2 * i + 1]);
+        const int32_t old = near[i];
         if (node_out) node_out[i] = old;
         const int32_t nw = P.node_old2new[old];
         const int64_t t = tile_of_node(P, nw);

@@ -278,15 +278,62 @@ int64_t hilbert_index(int64_t W, int64_t H, int64_t cx, int64_t cy) {
     }
 }
 
-int32_t nearest_node(const Plan& plan, double px, double py) {
-    int32_t best = 0;
-    double bd = INFINITY;
-    for (int64_t i = 0; i < plan.nn; ++i) {
-        const double dx = plan.node_xy[2 * i] - px, dy = plan.node_xy[2 * i + 1] - py;
-        const double d = dx * dx + dy * dy;
-        if (d < bd) { bd = d; best = (int32_t)i; }
+void nearest_nodes(const Plan& plan, int64_t n, const double* xy, int32_t* out) {
+    if (n <= 0) return;
+    const int64_t nn = plan.nn;
+    const double* nxy = plan.node_xy.data();
+    // nodes bucketed on a uniform grid of about two nodes per cell over their bounding box
+    double x0 = nxy[0], x1 = nxy[0], y0 = nxy[1], y1 = nxy[1];
+    for (int64_t i = 1; i < nn; ++i) {
+        x0 = std::min(x0, nxy[2 * i]); x1 = std::max(x1, nxy[2 * i]);
+        y0 = std::min(y0, nxy[2 * i + 1]); y1 = std::max(y1, nxy[2 * i + 1]);
     }
-    return best;
+    const double w = std::max(x1 - x0, 1e-300), hgt = std::max(y1 - y0, 1e-300);
+    const double h = std::max(std::sqrt(2.0 * w * hgt / (double)nn), std::max(w, hgt) / 65536.0);
+    const int64_t gx = std::max<int64_t>(1, std::min<int64_t>(65536, (int64_t)(w / h) + 1));
+    const int64_t gy = std::max<int64_t>(1, std::min<int64_t>(65536, (int64_t)(hgt / h) + 1));
+    auto cell_x = [&](double x) { return std::min<int64_t>(gx - 1, std::max<int64_t>(0, (int64_t)std::floor((x - x0) / h))); };
+    auto cell_y = [&](double y) { return std::min<int64_t>(gy - 1, std::max<int64_t>(0, (int64_t)std::floor((y - y0) / h))); };
+    std::vector<int64_t> start(gx * gy + 1, 0);
+    std::vector<int32_t> ids(nn);
+    for (int64_t i = 0; i < nn; ++i) start[cell_y(nxy[2 * i + 1]) * gx + cell_x(nxy[2 * i]) + 1]++;
+    for (int64_t c = 0; c < gx * gy; ++c) start[c + 1] += start[c];
+    {
+        std::vector<int64_t> fill(start.begin(), start.end() - 1);
+        for (int64_t i = 0; i < nn; ++i) ids[fill[cell_y(nxy[2 * i + 1]) * gx + cell_x(nxy[2 * i])]++] = (int32_t)i;
+    }
+    for (int64_t k = 0; k < n; ++k) {
+        const double px = xy[2 * k], py = xy[2 * k + 1];
+        const int64_t cx = cell_x(px), cy = cell_y(py);
+        int32_t best = -1;
+        double bd = INFINITY;
+        // rings of cells at Chebyshev distance r around the point's (clamped) cell; every node
+        // outside the (2r+1)^2 block lies at least `gap` from the point
+        for (int64_t r = 0;; ++r) {
+            for (int64_t yy = cy - r; yy <= cy + r; ++yy) {
+                if (yy < 0 || yy >= gy) continue;
+                const bool edge_row = yy == cy - r || yy == cy + r;
+                for (int64_t xx = cx - r; xx <= cx + r; xx += (edge_row || r == 0) ? 1 : 2 * r) {
+                    if (xx < 0 || xx >= gx) continue;
+                    const int64_t c = yy * gx + xx;
+                    for (int64_t t = start[c]; t < start[c + 1]; ++t) {
+                        const int32_t i = ids[t];
+                        const double dx = nxy[2 * i] - px, dy = nxy[2 * i + 1] - py;
+                        const double d = dx * dx + dy * dy;
+                        if (d < bd || (d == bd && i < best)) { bd = d; best = i; }
+                    }
+                }
+            }
+            if (cx - r <= 0 && cy - r <= 0 && cx + r >= gx - 1 && cy + r >= gy - 1) break;   // all cells seen
+            const double bx0 = x0 + (double)(cx - r) * h, bx1 = x0 + (double)(cx + r + 1) * h;
+            const double by0 = y0 + (double)(cy - r) * h, by1 = y0 + (double)(cy + r + 1) * h;
+            const double gap = std::min(std::min(px - bx0, bx1 - px), std::min(py - by0, by1 - py));
+            // stop once nothing outside the block can be as close (a relative margin covers the
+            // rounding of the block edges; equal distances must still be compared by id)
+            if (best >= 0 && gap > 0.0 && gap * gap > bd * (1.0 + 1e-9)) break;
+        }
+        out[k] = best;
+    }
 }
 
 // Element order of the benchmark section's node-walk strategies (Sec. 5): a breadth-first
@@ -378,8 +425,8 @@ void build_tiles(Plan& P, int tile_elems, int tile_items, int max_owned, bool sp
     // accum[v]: the node takes an accumulator slot. With split_single only the nodes on an
     // element's edge do (those of two or more elements and those on the domain boundary);
     // the element-interior nodes of a quadrilateral are finished by their element alone.
-    std::vector<uint8_t> accum(P.nn, split_single ? 0 : 1);
-    if (split_single)
+    std::vector<uint8_t> accum(P.nn, split_single && P.nvpe != 3 ? 0 : 1);
+    if (split_single && P.nvpe != 3)
         for (int64_t q = 0; q < nq; ++q) {
             const int64_t a = q % P.n, b = q / P.n;
             if (a == 0 || a == P.p || b == 0 || b == P.p)

@@ -117,8 +117,10 @@ int64_t hilbert_index(int64_t W, int64_t H, int64_t cx, int64_t cy);
 // Returns false when more than 64 colours would be needed.
 bool colour_elements(Plan& plan);
 
-// Nearest global node (original numbering) of a point; ties -> lowest id.
-int32_t nearest_node(const Plan& plan, double x, double y);
+// Nearest global node (original numbering) of each of n points xy[2n]; equal distances go
+// to the lowest id (the same node as a scan of all nodes). The nodes are bucketed on a grid
+// once per call, so a call costs O(nn + n * nodes near each point).
+void nearest_nodes(const Plan& plan, int64_t n, const double* xy, int32_t* out);
 
 // Geometric factors of one element (original numbering) at its (p+1)^2 GLL points.
 void element_geometry(const Plan& plan, const MeshIn& mesh, int64_t e, double* g11, double* g12,

@@ -41,7 +41,10 @@ int main(int argc, char** argv) {
                 int code = 0;
                 const std::string err = sem::build_plan(m, o, P, code);
                 if (!err.empty()) { std::fprintf(stderr, "%s: %s\n", argv[f], err.c_str()); return 1; }
-                const int32_t node = sem::nearest_node(P, vxy[0] + 0.3, vxy[1] + 0.2);
+                const double pts[6] = {vxy[0] + 0.3, vxy[1] + 0.2, -1e6, 3e6, vxy[2], vxy[3]};
+                int32_t near[3];
+                sem::nearest_nodes(P, 3, pts, near);
+                const int32_t node = near[0];
                 std::printf("%s order %d split %d: nodes %lld tiles %zu halo %zu colours %d node %d\n", argv[f],
                             order, split, (long long)P.nn, P.tile_eb.size() - 1, P.halo.size(), P.n_colours, node);
             }

@@ -128,6 +128,31 @@ def test_dt_nodes_and_snapping_match_oracle(semlib):
     assert s.info()["n_receivers"] == wl.rec_xy.shape[0]
 
 
+@pytest.mark.parametrize("name,kw", [("layered1024", dict(n=30)), ("tri2000", dict(n=24, p=5)),
+                                     ("graded1414", dict(n=12, p=5))])
+def test_snapping_is_the_nearest_node_everywhere(semlib, name, kw):
+    """Point snapping (a bucket-grid search in the library) returns the node a scan of all
+    nodes returns: random points inside and far outside the mesh, points on nodes, and
+    midpoints of node pairs (equal distances go to the lowest id)."""
+    wl = workloads.workload(name, **kw)
+    s = semlib.Simulator(wl.vxy, wl.quads, wl.c2, wl.p, device=-1)
+    xy = s.node_coords()
+    lo, hi = xy.min(0), xy.max(0)
+    rng = np.random.default_rng(5)
+    pts = [rng.uniform(lo, hi, size=(600, 2)),
+           rng.uniform(lo - 0.5 * (hi - lo), hi + 0.5 * (hi - lo), size=(200, 2)),
+           xy[rng.choice(len(xy), 100, replace=False)]]
+    a, b = rng.choice(len(xy), 100), rng.choice(len(xy), 100)
+    pts.append(0.5 * (xy[a] + xy[b]))
+    near = rng.choice(len(xy), 100)
+    pts.append(0.5 * (xy[near] + xy[np.argsort(np.abs(xy[:, 0] - xy[near[0], 0]))[1]]))
+    pts = np.concatenate(pts)
+    np.testing.assert_array_equal(s.set_receivers(pts), solver.snap_to_nodes(pts, xy))
+    np.testing.assert_array_equal(s.set_sources(pts[:300], np.zeros(300, np.int32), 10.0),
+                                  solver.snap_to_nodes(pts[:300], xy))
+    s.close()
+
+
 def test_tiling_covers_every_node_once(semlib):
     wl = workloads.workload("layered1024", n=40)
     for te in (16, 50, 128):
