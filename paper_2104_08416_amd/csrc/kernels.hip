@@ -28,14 +28,6 @@
 #ifndef SEM_MIN_WAVES_F64
 #define SEM_MIN_WAVES_F64 1
 #endif
-// passes of the triangle kernel whose loads are issued together
-#ifndef TRI_NP
-#define TRI_NP 2
-#endif
-// triangle kernel: request the next group's node ids and records before this group's compute
-#ifndef TRI_PF
-#define TRI_PF 1
-#endif
 
 namespace sem {
 namespace {
@@ -1215,8 +1207,8 @@ __global__ void __attribute__((amdgpu_flat_work_group_size(RB, RB))) tri_rows_ke
         s3[m] = a.tri_S[(2 * NQ + qrow) * NQ + m];
     }
     // NP passes at a time: every pass's node ids and records are requested first, then every
-    // pass's gathers, so NP passes cost about one memory round trip; with TRI_PF the ids and
-    // records of the next NP passes are requested before this group's compute. The loads are
+    // pass's gathers, so NP passes cost about one memory round trip, and the ids and records
+    // of the next NP passes are requested before this group's compute. The loads are
     // unconditional (an inactive lane reads at the buffer's byte count, which returns 0
     // without touching memory), so the wait counts stay exact through the loop.
     auto fetch = [&](int base, int (&es)[NP], int (&node)[NP], bool (&act)[NP], T (&rec)[NP][4]) {
@@ -1246,33 +1238,27 @@ __global__ void __attribute__((amdgpu_flat_work_group_size(RB, RB))) tri_rows_ke
     int es_n[NP], node_n[NP];
     bool act_n[NP];
     T rec_n[NP][4];
-    if (TRI_PF) fetch(0, es_n, node_n, act_n, rec_n);
+    fetch(0, es_n, node_n, act_n, rec_n);
     for (int base = 0; base < n_items; base += NP * EPB) {
         int es[NP], node[NP];
         bool act[NP];
         T rec[NP][4], uq[NP];
-        if (TRI_PF) {
 #pragma unroll
-            for (int pp = 0; pp < NP; ++pp) {
-                es[pp] = es_n[pp];
-                node[pp] = node_n[pp];
-                act[pp] = act_n[pp];
+        for (int pp = 0; pp < NP; ++pp) {
+            es[pp] = es_n[pp];
+            node[pp] = node_n[pp];
+            act[pp] = act_n[pp];
 #pragma unroll
-                for (int c = 0; c < 4; ++c) rec[pp][c] = rec_n[pp][c];
-            }
-        } else {
-            fetch(base, es, node, act, rec);
+            for (int c = 0; c < 4; ++c) rec[pp][c] = rec_n[pp][c];
         }
 #pragma unroll
         for (int pp = 0; pp < NP; ++pp)
             uq[pp] = bload<T>(r_u, act[pp] ? (uint32_t)node[pp] * (uint32_t)sizeof(T) : a.state_bytes);
-        if (TRI_PF) {
-            // keep the order gathers, next ids, compute: a gather moved after the next ids
-            // would make the first stage write wait for those ids as well
-            __builtin_amdgcn_sched_barrier(0);
-            fetch(base + NP * EPB, es_n, node_n, act_n, rec_n);
-            __builtin_amdgcn_sched_barrier(0);
-        }
+        // keep the order gathers, next ids, compute: a gather moved after the next ids would
+        // make the first stage write wait for those ids as well
+        __builtin_amdgcn_sched_barrier(0);
+        fetch(base + NP * EPB, es_n, node_n, act_n, rec_n);
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int pp = 0; pp < NP; ++pp) {
             const int k = base + pp * EPB + slot;
@@ -1361,9 +1347,10 @@ __global__ void __attribute__((amdgpu_flat_work_group_size(RB, RB))) tri_rows_ke
 
 template <typename T, int P, int RB>
 hipError_t launch_tri(int64_t n_tiles, const StepArgs<T>& a, hipStream_t st) {
-    // FP32: TRI_NP passes (about 100 VGPRs, four waves per SIMD either way); FP64: one pass
-    // (two would drop to two waves per SIMD)
-    constexpr int NP = sizeof(T) == 4 ? TRI_NP : 1;
+    // FP32: two passes per group (107 VGPRs, four waves per SIMD; on the 250k-triangle p = 5
+    // mesh one pass ran 6% slower and three 1% slower); FP64: one pass (two would drop to two
+    // waves per SIMD)
+    constexpr int NP = sizeof(T) == 4 ? 2 : 1;
     auto fn = a.grad != nullptr ? tri_rows_kernel<T, P, RB, NP, true> : tri_rows_kernel<T, P, RB, NP, false>;
     const size_t lds = tri_lds_bytes(P, RB, a.lds_own, sizeof(T));
     if (lds > 65536) {
