@@ -112,6 +112,7 @@ def leg_summary(sim, sec_per_step, label):
         "halo_ratio": inf["halo_elements"] / inf["n_elements"],
         "setup_s": inf["setup_seconds"],
         "reorder_s": inf["reorder_seconds"],
+        "n_colours": inf["n_colours"],
     }
 
 
@@ -427,15 +428,15 @@ def main():
                                   "time_vs_lds_atomic": lg["us_per_step"] / main_leg["us_per_step"]}
             sc_sim.close()
     if "orders" in legs:
-        out["orders"] = {"hilbert": {k: main_leg[k] for k in ("gdof_steps_per_s", "hbm_frac", "halo_ratio",
-                                                              "setup_s", "reorder_s")}}
+        order_keys = ("gdof_steps_per_s", "us_per_step", "hbm_frac", "halo_ratio", "setup_s", "reorder_s",
+                      "n_colours")
+        out["orders"] = {"hilbert": {k: main_leg[k] for k in order_keys}}
         for order in ("morton", "lex", "random", "connectivity", "distance"):
             log(f"[bench] order {order}")
             so, _ = make_sim(sem, wl, "f32", order)
             spo, _, _ = time_steps(torch, so, min(args.steps, 200), 5)
             lg = leg_summary(so, spo, order)
-            out["orders"][order] = {k: lg[k] for k in ("gdof_steps_per_s", "hbm_frac", "halo_ratio",
-                                                       "setup_s", "reorder_s")}
+            out["orders"][order] = {k: lg[k] for k in order_keys}
             so.close()
     if "heun" in legs:
         log("[bench] heun leg: the first-order u-v system with Heun, layered1024 p=4 FP32")
@@ -468,7 +469,7 @@ def main():
             spg, _, _ = time_steps(torch, sg, min(args.steps, 100), 5)
             lg = leg_summary(sg, spg, f"graded1414 p5 f32 {order}")
             out["graded"][order] = {k: lg[k] for k in ("gdof_steps_per_s", "us_per_step", "hbm_frac",
-                                                       "halo_ratio", "setup_s", "reorder_s")}
+                                                       "halo_ratio", "setup_s", "reorder_s", "n_colours")}
             sg.close()
     if "batch" in legs:
         log("[bench] batch leg: 512^2 p=4, 64 shots FP32 vs single-shot FP64")
