@@ -41,7 +41,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
-ALL_LEGS = ("main", "fp64", "scatter", "heun", "tri", "batch", "adjoint", "orders", "graded", "cpu")
+ALL_LEGS = ("main", "fp64", "scatter", "heun", "tri", "batch", "adjoint", "orders", "graded", "shard", "cpu")
 CHUNKS = 5                     # the timed steps are event-timed in this many chunks (median)
 KERNEL_SOURCES = ("kernels.hip", "kernels.h", "api.hip", "plan.cpp", "plan.h")
 HEADLINE_PROFILE = os.path.join(ROOT, "profiles", "step_rows_kernel_layered1024_f32_hilbert.md")
@@ -405,7 +405,41 @@ def main():
     main_leg = leg_summary(sim, sps, label)
     main_leg["median_chunk_us_per_step"] = sps_med * 1e6
     log(f"[bench] headline {main_leg['gdof_steps_per_s']:.1f} GDOF*steps/s, {main_leg['us_per_step']:.1f} us/step")
+    elem_new2old, _ = sim.permutations()
+    main_dt = sim.dt
     sim.close()
+
+    if "shard" in legs and args.workload == "layered1024" and wl.quads.shape[1] == 4:
+        # One GPU's share of an 8-way split of the single-shot step (each GPU takes a
+        # contiguous eighth of the curve's element order): that eighth as a mesh of its own, at
+        # its real shape, and the interface an 8-way split would exchange per step (no
+        # exchange is run: this build uses one GPU)
+        G = 8
+        ne = wl.quads.shape[0]
+        log(f"[bench] shard leg: the first 1/{G} of the Hilbert element order as one GPU's share")
+        chunk = np.sort(elem_new2old[: ne // G])
+        verts, inv = np.unique(wl.quads[chunk].ravel(), return_inverse=True)
+        sq = inv.reshape(-1, 4).astype(np.int32)
+        ss = sem.Simulator(wl.vxy[verts], sq, wl.c2[chunk], wl.p, precision="f32", order="hilbert", dt=main_dt)
+        ssps, _, _ = time_steps(torch, ss, min(args.steps, 300), args.warmup, record=False)
+        lg = leg_summary(ss, ssps, f"layered1024 p4 f32 hilbert S=1, elements [0, E/{G}) of the curve")
+        ss.close()
+        inside = np.zeros(ne, bool)
+        inside[chunk] = True
+        shared_v = np.intersect1d(np.unique(wl.quads[inside]), np.unique(wl.quads[~inside]))
+
+        def edges(q):
+            e = np.stack([q, np.roll(q, -1, axis=1)], axis=2).reshape(-1, 2)
+            e.sort(axis=1)
+            return np.unique(e[:, 0].astype(np.int64) * wl.vxy.shape[0] + e[:, 1])
+
+        shared_e = np.intersect1d(edges(wl.quads[inside]), edges(wl.quads[~inside]))
+        iface = int(shared_v.size + (wl.p - 1) * shared_e.size)
+        out["shard"] = {k: lg[k] for k in ("label", "gdof_steps_per_s", "us_per_step", "hbm_frac", "n_nodes",
+                                             "n_elements", "halo_ratio")}
+        out["shard"].update({"gpus_in_split": G, "rate_vs_whole_mesh": lg["gdof_steps_per_s"] /
+                             main_leg["gdof_steps_per_s"], "interface_nodes": iface,
+                             "interface_bytes_fp32": 4 * iface})
 
     if "fp64" in legs:
         log("[bench] fp64 leg")
