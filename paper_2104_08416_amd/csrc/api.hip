@@ -480,9 +480,10 @@ int upload_geometry(sem_ctx* c) {
     // the kernels address these arrays with 32-bit byte offsets
     const int64_t ni = (int64_t)(P.p - 1) * (P.p - 1);
     if (tri_kernel(c)) {
-        // conn [E + H][nq], record [E + H][4] = g11, g12, g22, c^2: the E elements in curve
-        // order, then a copy of each halo element's row in the order of the halo list (the
-        // kernel then finds a halo row without first loading its element index)
+        // conn [E + H][nq], record [E + H][4] = c_12, c_23, c_13, c^2 (the coefficients of
+        // E_12 = Sxx, E_23, E_13 in K_e / c^2: g11 + g12, -g12, g12 + g22): the E elements in
+        // curve order, then a copy of each halo element's row in the order of the halo list
+        // (the kernel then finds a halo row without first loading its element index)
         const int64_t nh = (int64_t)P.halo.size(), rows = ne + nh;
         if ((double)rows * nq * 4.0 >= 4294967296.0 || (double)rows * 4 * sizeof(T) >= 4294967296.0)
             return fail(c, SEM_ERR_INVALID_ARG, "element arrays exceed 4 GiB (32-bit buffer offsets)");
@@ -491,7 +492,10 @@ int upload_geometry(sem_ctx* c) {
         for (int64_t k = 0; k < rows; ++k) {
             const int64_t e = c->elem_slot[k < ne ? k : P.halo[k - ne]];
             for (int64_t q = 0; q < nq; ++q) cb[k * nq + q] = P.conn_soa[q * ne + e];
-            for (int j = 0; j < 3; ++j) gb[k * 4 + j] = P.tri_G[(size_t)j * ne + e];
+            const double g11 = P.tri_G[e], g12 = P.tri_G[(size_t)ne + e], g22 = P.tri_G[(size_t)2 * ne + e];
+            gb[k * 4 + 0] = g11 + g12;
+            gb[k * 4 + 1] = -g12;
+            gb[k * 4 + 2] = g12 + g22;
             gb[k * 4 + 3] = P.c2[e];
         }
         SEM_HIP(c, upload(c, c->conn, cb));
@@ -997,7 +1001,9 @@ int sem_create(const sem_mesh* mesh, const sem_options* opt, sem_ctx** out) {
     po.tile_elems = opt->tile_elems;
     // measured on the layered 1024^2 p=4 mesh (FP64 LDS accumulators): 512 threads x 1 pass
     // in both precisions
-    const int row_block = opt->block_threads > 0 ? opt->block_threads : 512;
+    // triangles default to 256 threads (on the 250k-triangle p = 5 mesh 256 threads with
+    // 240-element tiles ran 2.5% (FP32) and 4.4% (FP64) faster than 512 with 336)
+    const int row_block = opt->block_threads > 0 ? opt->block_threads : (nvpe == 3 ? 256 : 512);
     if (row_block != 256 && row_block != 512 && row_block != 1024) {
         g_create_error = "block_threads must be 256, 512 or 1024";
         delete c;
@@ -1014,12 +1020,12 @@ int sem_create(const sem_mesh* mesh, const sem_options* opt, sem_ctx** out) {
     po.tile_items = pick_tile_items(opt->p, c->SL, row_block, opt->tile_items);
     if (opt->tile_items <= 0 && c->SL == 1) po.tile_items = epb;
     if (nvpe == 3 && opt->tile_items <= 0) {
-        // triangles: fourteen passes of 64 / nq elements per wave (measured on the
-        // 250k-triangle p = 5 mesh with 512 threads: 336 own + halo elements a tile ran 10%
-        // (FP32) and 12% (FP64) faster than 192; larger tiles no longer fit two FP32
-        // workgroups in a CU's LDS, see the owned-node cap below)
+        // triangles: tiles of about 240 own + halo elements in whole workgroup passes of
+        // 64 / nq elements per wave (twenty passes with 256 threads at p = 5; measured there
+        // against 96 and 168: 3% and 1% faster in FP32, 4% and 1% in FP64), and never more owned
+        // nodes than the LDS of the resident workgroups allows (the cap below)
         const int epb_tri = (64 / sem::tri_nq(opt->p)) * (row_block / 64);
-        po.tile_items = 14 * epb_tri;
+        po.tile_items = std::max(1, (240 + epb_tri / 2) / epb_tri) * epb_tri;
     }
     // 64 shots: tiles are bounded by the LDS accumulator, not by an element count
     if (opt->tile_items <= 0 && c->SL == 64) po.tile_items = 1 << 20;
@@ -1028,10 +1034,9 @@ int sem_create(const sem_mesh* mesh, const sem_options* opt, sem_ctx** out) {
     po.max_owned = pick_max_owned(c->SL, opt->precision, opt->lds_bytes);
     if (nvpe == 3 && opt->lds_bytes <= 0) {
         // triangles: bound a tile's owned nodes so that the workgroups the registers allow on
-        // a CU (FP32 about 110 VGPRs, 16 waves a CU; FP64 about 190, 8 waves) also fit its
-        // 160 KB of LDS: on the 250k-triangle mesh, FP32 tiles one pass past that bound ran
-        // 38% slower
-        const int per_cu = std::max(1, (opt->precision == SEM_F64 ? 8 : 16) / (row_block / 64));
+        // a CU (p = 5: FP32 88 VGPRs, 20 waves a CU; FP64 113, 16 waves) also fit its 160 KB of
+        // LDS: on the 250k-triangle mesh, FP32 tiles one pass past that bound ran 38% slower
+        const int per_cu = std::max(1, (opt->precision == SEM_F64 ? 16 : 20) / (row_block / 64));
         const size_t word = opt->precision == SEM_F64 ? 8 : 4;
         const size_t stage = sem::tri_lds_bytes(opt->p, row_block, 0, word);
         const size_t budget = 163840 / (size_t)per_cu;

@@ -75,7 +75,9 @@ struct StepArgs {
     const int32_t* src_node;
     const int32_t* rec_node;
     int32_t n_src_pts, n_rec_pts;
-    // triangles: reference matrices [3][nq][nq] (Sxx, Sxy + Syx, Syy) of the nodal basis
+    // triangles: reference matrices [3][nq][nq] (Sxx, Sxy + Syx, Syy) of the nodal basis; the
+    // kernel reads Sxx only (E_23 = Sxx + Syy - Sxy and E_13 = Syy are Sxx under the vertex
+    // rotations of the node numbering)
     const T* tri_S;
     // 1D GLL nodes, weights and derivative matrix D[i*(p+1) + j] = l_j'(xi_i)
     T xi[kMaxP + 1];
@@ -106,8 +108,9 @@ hipError_t launch_border(const StepArgs<T>& a, const int32_t* nodes, int64_t n_n
 template <typename T>
 hipError_t launch_global_points(const StepArgs<T>& a, int phase, hipStream_t stream);
 
-// geo = kGeoTri + threads (256/512/1024): the triangle kernel (p odd; conn [E][nq], records
-// [E][4] = det J J^-1 J^-T (11, 12, 22), c^2; reference matrices in tri_S), one shot per launch.
+// geo = kGeoTri + threads (256/512/1024): the triangle kernel (p odd; conn [E + H][nq], records
+// [E + H][4] = c_12, c_23, c_13, c^2 with K_e = c^2 (c_12 E_12 + c_23 E_23 + c_13 E_13); Sxx in
+// tri_S), one shot per launch.
 // geo = threads * 8 + passes (threads 256/512/1024, passes 1/2/4 batched per round of
 // loads): single-shot row kernel, geometric factors computed in-kernel (shot_lanes 1);
 // geo = kGeoShots + threads (256/512/1024): 64-shot kernel, one wave per element

@@ -1147,6 +1147,23 @@ hipError_t launch_elems_t(int threads, bool atomic, const StepArgs<T>& a, hipStr
     }
 }
 
+// Vertex rotations of the triangle's local node numbering (node (i, j) at index
+// j (P + 1) - j (j - 1) / 2 + i, k = P - i - j): s23 takes node (i, j, k) to (j, k, i), s13 to
+// (k, i, j), s13 = s23^-1. The host checks that they carry Sxx to E_23 and E_13.
+template <int P>
+struct TriRot {
+    static constexpr int NQ = (P + 1) * (P + 2) / 2;
+    int s23[NQ], s13[NQ];
+    constexpr TriRot() : s23(), s13() {
+        for (int j = 0; j <= P; ++j)
+            for (int i = 0; i + j <= P; ++i) {
+                const int k = P - i - j, q = j * (P + 1) - j * (j - 1) / 2 + i;
+                s23[q] = k * (P + 1) - k * (k - 1) / 2 + j;
+                s13[q] = i * (P + 1) - i * (i - 1) / 2 + k;
+            }
+    }
+};
+
 // ---------------------------------------------------------------------------------------
 // The paper's own element (Sec. 4.2): affine triangles with nq = (p+1)(p+2)/2 local nodes on
 // the Blyth-Pozrikidis grid, single shot, owner-tile LDS accumulation with halo
@@ -1198,14 +1215,20 @@ __global__ void __attribute__((amdgpu_flat_work_group_size(RB, RB))) tri_rows_ke
     int qi = q, qj = 0;
     while (qj <= P && qi >= P + 1 - qj) { qi -= P + 1 - qj; ++qj; }
     const bool interior = qi >= 1 && qj >= 1 && P - qi - qj >= 1;
-    T s1[NQ], s2[NQ], s3[NQ];
+    // Row q of Sxx = E_12 stays in registers for the launch. E_23 and E_13 are Sxx with rows
+    // and columns permuted by s = s_23, s_13 (the vertex symmetry of the node set), so
+    // (E u)_q = sum_m Sxx[s(q)][m] u_{s^-1(m)}: lane s(q) forms that sum from its own row and
+    // the element's values read through s^-1, and lane q takes it with a lane shuffle. A lane
+    // holds 21 matrix entries at p = 5 instead of 63.
+    T s1[NQ];
     const int qrow = kw < EPW ? q : 0;
 #pragma unroll
-    for (int m = 0; m < NQ; ++m) {
-        s1[m] = a.tri_S[qrow * NQ + m];
-        s2[m] = a.tri_S[(NQ + qrow) * NQ + m];
-        s3[m] = a.tri_S[(2 * NQ + qrow) * NQ + m];
-    }
+    for (int m = 0; m < NQ; ++m) s1[m] = a.tri_S[qrow * NQ + m];
+    constexpr TriRot<P> rot{};
+    // lanes s23(q), s13(q) of this element: nodes (qj, qk, qi) and (qk, qi, qj)
+    const int qk = P - qi - qj;
+    const int src23 = lane - q + qk * (P + 1) - qk * (qk - 1) / 2 + qj;
+    const int src13 = lane - q + qi * (P + 1) - qi * (qi - 1) / 2 + qk;
     // NP passes at a time: every pass's node ids and records are requested first, then every
     // pass's gathers, so NP passes cost about one memory round trip, and the ids and records
     // of the next NP passes are requested before this group's compute. The loads are
@@ -1268,20 +1291,20 @@ __global__ void __attribute__((amdgpu_flat_work_group_size(RB, RB))) tri_rows_ke
                 wave_sync();                           // earlier reads of the stage are done
                 st[q] = u;
                 wave_sync();
-                // Every row of the reference matrices sums to zero (K_e 1 = 0), so the row
-                // applies to u_m - u_q: the common part of the element's values cancels before
-                // rounding and the rounded matrices keep the exact null space (in FP32 the plain
-                // product drifts by the rounding of the row sums, which acts on the mean field
-                // every step)
-                T y1 = T(0), y2 = T(0), y3 = T(0);
+                // Every row of the reference matrices sums to zero (K_e 1 = 0), so a row
+                // applies to the differences from the lane's own value: the common part of the
+                // element's values cancels before rounding and the rounded matrices keep the
+                // exact null space (in FP32 the plain product drifts by the rounding of the row
+                // sums, which acts on the mean field every step)
+                T y12 = T(0), z23 = T(0), z13 = T(0);
 #pragma unroll
                 for (int m = 0; m < NQ; ++m) {
-                    const T um = st[m] - u;
-                    y1 += s1[m] * um;
-                    y2 += s2[m] * um;
-                    y3 += s3[m] * um;
+                    y12 += s1[m] * (st[m] - u);
+                    z23 += s1[m] * (st[rot.s13[m]] - u);          // u read through s23^-1
+                    z13 += s1[m] * (st[rot.s23[m]] - u);          // u read through s13^-1
                 }
-                const T r = rec[pp][0] * y1 + rec[pp][1] * y2 + rec[pp][2] * y3;    // (Khat_e u_e)_q
+                const T y23 = __shfl(z23, src23, 64), y13 = __shfl(z13, src13, 64);
+                const T r = rec[pp][0] * y12 + rec[pp][1] * y23 + rec[pp][2] * y13;    // (Khat_e u_e)_q
                 if constexpr (GRAD) {
                     if (k < n_own_el) dot = r * bload<T>(r_pair, (uint32_t)node[pp] * (uint32_t)sizeof(T));
                 }

@@ -582,6 +582,8 @@ std::string build_plan(const MeshIn& m, const PlanOptions& opt, Plan& P, int& co
         G0.assign((size_t)3 * ne, 0.0);
         err = tri_reference(P.p, P.xi, P.tri_xy, P.tri_w, P.tri_S);
         if (!err.empty()) return err;
+        err = tri_symmetry(P.p, P.tri_S);
+        if (!err.empty()) return err;
         std::vector<double> px(nq), py(nq);
         for (int64_t e = 0; e < ne; ++e) {
             const int32_t* t = m.quad + 3 * e;

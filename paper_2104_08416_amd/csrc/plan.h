@@ -92,6 +92,10 @@ int tri_nq(int p);
 int tri_lidx(int i, int j, int p);
 std::string tri_reference(int p, const std::vector<double>& gll_x, std::vector<double>& xy,
                           std::vector<double>& w, std::vector<double>& S);
+// Checks the vertex symmetry the triangle kernel relies on: E_23 = Sxx + Syy - Sxy and
+// E_13 = Syy are Sxx with rows and columns permuted by the vertex rotations (i, j, k) ->
+// (j, k, i) and (k, i, j) of the local node numbering.
+std::string tri_symmetry(int p, const std::vector<double>& S);
 std::string tri_number_nodes(const MeshIn& mesh, int p, std::vector<int32_t>& conn, int64_t& nn);
 
 // Fills `plan` or returns a non-empty error string; `code` receives the sem_status.

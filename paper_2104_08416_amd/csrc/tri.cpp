@@ -165,6 +165,38 @@ std::string tri_reference(int p, const std::vector<double>& gll_x, std::vector<d
     return "";
 }
 
+std::string tri_symmetry(int p, const std::vector<double>& S) {
+    // On an affine triangle, with n_i the gradients of the barycentric coordinates on the
+    // reference triangle (n_1 = (-1, -1), n_2 = (1, 0), n_3 = (0, 1)) and c_ij = -n_i.G n_j,
+    //   g11 Sxx + g12 Sxy + g22 Syy = c_12 E_12 + c_23 E_23 + c_13 E_13,
+    //   E_12 = Sxx, E_13 = Syy, E_23 = Sxx + Syy - Sxy,  c_12 = g11 + g12, c_23 = -g12,
+    //   c_13 = g12 + g22.
+    // The node set is invariant under the rotations of the vertices, and E_23, E_13 are Sxx
+    // seen from rotated vertices: E[q][m] = Sxx[s(q)][s(m)] with s_23 taking node (i, j, k) to
+    // node (j, k, i) and s_13 = s_23^-1 taking it to (k, i, j). The triangle kernel relies on
+    // exactly these two maps; checked here entry by entry.
+    const int nq = tri_nq(p);
+    auto sxx = [&](int a, int b) { return S[(size_t)a * nq + b]; };
+    auto sxy = [&](int a, int b) { return S[(size_t)(nq + a) * nq + b]; };
+    auto syy = [&](int a, int b) { return S[(size_t)(2 * nq + a) * nq + b]; };
+    std::vector<int> s23(nq), s13(nq);
+    for (int j = 0; j <= p; ++j)
+        for (int i = 0; i + j <= p; ++i) {
+            const int k = p - i - j, q = tri_lidx(i, j, p);
+            s23[q] = tri_lidx(j, k, p);
+            s13[q] = tri_lidx(k, i, p);
+        }
+    double scale = 0.0, err = 0.0;
+    for (int a = 0; a < nq; ++a)
+        for (int b = 0; b < nq; ++b) {
+            scale = std::max(scale, std::fabs(sxx(a, b)));
+            err = std::max(err, std::fabs(sxx(a, b) + syy(a, b) - sxy(a, b) - sxx(s23[a], s23[b])));
+            err = std::max(err, std::fabs(syy(a, b) - sxx(s13[a], s13[b])));
+        }
+    if (!(err <= 1e-12 * scale)) return "the triangle's reference matrices lack the vertex symmetry of the nodes";
+    return "";
+}
+
 std::string tri_number_nodes(const MeshIn& m, int p, std::vector<int32_t>& conn, int64_t& nn) {
     const int nq = tri_nq(p);
     const int64_t ne = m.ne, nv = m.nv;
