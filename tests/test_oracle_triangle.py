@@ -208,3 +208,39 @@ def test_sampled_rows_match_assembly():
     r, M = triangle.sampled_rows(vxy, tris, c2, 5, sem.conn, nodes, u)
     np.testing.assert_allclose(r, (sem.K @ u)[nodes], rtol=1e-13, atol=1e-13 * np.abs(sem.K @ u).max())
     np.testing.assert_allclose(M, sem.mass[nodes], rtol=1e-13)
+
+
+@pytest.mark.parametrize("p", [1, 3, 5, 7])
+def test_stiffness_is_cotangent_weighted_rotations_of_one_matrix(p):
+    """On an affine triangle the element stiffness is a sum over the three vertex pairs,
+    K_e = sum c_ij E_ij with c_ij = -det J grad(lambda_i).grad(lambda_j) (the cotangent
+    weights), and the three E_ij are one matrix seen from rotated vertices: E[q][m] =
+    E_12[s(q)][s(m)] for the node rotations (i, j, k) -> (j, k, i) and (k, i, j), since the
+    Blyth-Pozrikidis node set is invariant under them (Sec. 4.2). Checked with the oracle's
+    exact basis: the matrices to 1e-12 and K_e of random triangles to 1e-12."""
+    Dx, Dy, om = triangle.reference_operators(p)
+    Sxx, Syy = (Dx.T * om) @ Dx, (Dy.T * om) @ Dy
+    Sxy = (Dx.T * om) @ Dy + (Dy.T * om) @ Dx
+    nodes = triangle.local_nodes(p)
+    s23 = np.array([triangle.local_index(j, p - i - j, p) for i, j in nodes])
+    s13 = np.array([triangle.local_index(p - i - j, i, p) for i, j in nodes])
+    E12, E23, E13 = Sxx, Sxx + Syy - Sxy, Syy
+    scale = np.abs(Sxx).max()
+    assert np.abs(E23 - Sxx[np.ix_(s23, s23)]).max() <= 1e-12 * scale
+    assert np.abs(E13 - Sxx[np.ix_(s13, s13)]).max() <= 1e-12 * scale
+    # the rotations are not trivial: Sxx itself is not invariant under them
+    assert np.abs(Sxx - Sxx[np.ix_(s23, s23)]).max() > 1e-3 * scale
+    rng = np.random.default_rng(31)
+    vxy = rng.uniform(-1.0, 1.0, size=(30, 2))
+    tris = np.arange(30).reshape(10, 3)
+    J, det = triangle.jacobians(vxy, tris)
+    flip = det < 0
+    tris[flip] = tris[flip][:, ::-1]
+    J, det = triangle.jacobians(vxy, tris)
+    Ke = triangle.element_stiffness(vxy, tris, p)
+    n = np.array([[-1.0, -1.0], [1.0, 0.0], [0.0, 1.0]])      # reference barycentric gradients
+    for e in range(len(tris)):
+        g = np.linalg.solve(J[e].T, n.T).T                    # physical gradients, [3, 2]
+        c = lambda a, b: -det[e] * (g[a] @ g[b])
+        K2 = c(0, 1) * E12 + c(1, 2) * E23 + c(0, 2) * E13
+        assert np.abs(K2 - Ke[e]).max() <= 1e-12 * np.abs(Ke[e]).max()
