@@ -461,8 +461,8 @@ __global__ void __launch_bounds__(BT)
         // requested now so that the loads overlap the contraction
         const bool upd = own && mode0;
         T vin[NI > 0 ? NI : 1];
-        // FP64 (no deferred stores) keeps these loads in branches: unconditional, they raised
-        // its registers from 166 to 218 (three waves per SIMD to two)
+        // FP64 (no deferred stores, so no exact wait to keep) issues these loads only where
+        // they are needed
         if (DEFER || upd) {
 #pragma unroll
             for (int b = 1; b < P; ++b)
