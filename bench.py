@@ -356,8 +356,8 @@ def main():
         print(profile_summary(args.profile_summary, args.kernel, args.steps, args.counter_steps, args.per_step))
         return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); multi-GPU sharding is a "
-              "design note, not part of this build.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the library has no "
+              "multi-GPU path; the `shard` leg measures one GPU's share of an 8-way split.", file=sys.stderr)
         sys.exit(2)
     legs = ("main",) if (args.quick or args.copy_calib) else tuple(x for x in args.legs.split(",") if x)
 
