@@ -374,7 +374,7 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     out = {}
     # plain device copy of 2^28 floats (1 GiB read + 1 GiB written per launch): the HBM rate
-    # a streaming kernel reaches on this machine, and the reference of the counter scaling
+    # a streaming kernel reaches on this device, and the reference of the counter scaling
     src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
     for _ in range(2):
@@ -413,7 +413,7 @@ def main():
         # One GPU's share of an 8-way split of the single-shot step (each GPU takes a
         # contiguous eighth of the curve's element order): that eighth as a mesh of its own, at
         # its real shape, and the interface an 8-way split would exchange per step (no
-        # exchange is run: this build uses one GPU)
+        # exchange is run: the library has no multi-GPU path)
         G = 8
         ne = wl.quads.shape[0]
         log(f"[bench] shard leg: the first 1/{G} of the Hilbert element order as one GPU's share")
@@ -543,7 +543,7 @@ def main():
                                       args.formulation) == ("layered1024", "f32", "hilbert", None, "auto",
                                                             "leapfrog") else None
     sec = main_leg["us_per_step"] / 1e6
-    # the same step against what it measurably moves and against the box's copy rate
+    # the same step against what it measurably moves and against the device's copy rate
     main_leg["measured_traffic_GBs"] = traffic / sec / 1e9 if traffic else None
     main_leg["measured_traffic_frac_of_peak"] = traffic / sec / 1e9 / HBM_PEAK_GBS if traffic else None
     main_leg["copy_GBs"] = copy_gbs
